@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Benchmark: N-1 scenario solves per second, batched vs plain PCG, on one MI355X.
+
+One step is one pass of the whole hot path over one batch: every single-branch
+outage of the grid (2,000-bus synthetic grid by default: 2,800 scenarios)
+solved by the device library's batched PCG - base residual, init, PCG to the
+tolerance, angles, flows, island flags and true residuals - with inputs
+already resident in HBM.  Printed as one JSON line (rank 0).
+
+Besides the contract fields the line carries:
+  * "plain": the same scenarios (a seeded sample) through the plain
+    per-scenario PCG of the same library, and the batched/plain ratio;
+  * "roofline": the PCG tile kernel's algorithmic HBM bytes per launch over
+    its average launch time (HIP events on the context's stream), against
+    the 8 TB/s HBM3E peak; "traffic" comes from the committed rocprofv3
+    counter summary when it was taken on the current kernel source;
+  * "cpu_baseline": the FP64 oracle's direct solve (sparse LU + extended
+    precision refinement per scenario, the paper's rebuild-per-scenario
+    reference) on a bounded sample, on the host cores;
+  * "verify": worst true residual, status counts, iteration statistics.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N-1 scenario solves/sec to 1e-10 residual, batched vs plain PCG; HBM GB/s %"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "pcg_tile_grid2k_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_kernels.hip")
+
+# Vector passes (8 bytes per row per scenario column each) of the tile kernel
+# as written: init writes delta, r, p, q; a forward sweep reads delta, p, r, q
+# and writes delta, r, y; a backward sweep reads y, r and writes z; the
+# direction update reads z, p and writes p; the product reads p and writes q.
+PASSES_INIT, PASSES_FWD, PASSES_BWD, PASSES_DIR, PASSES_SPMM = 4, 7, 3, 3, 2
+
+
+def kernel_digest() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def tile_bytes(info: dict, K: int, S: int) -> float:
+    """Algorithmic bytes one tile of S columns moves over K iterations."""
+    nr = info["n_r"]
+    vec = 8.0 * nr * S
+    fwd = PASSES_FWD * vec + 12.0 * info["nnz_l"] + 4.0 * (nr + 1)
+    bwd = PASSES_BWD * vec + 12.0 * (info["nnz_u"] - nr) + 12.0 * nr + 4.0 * nr
+    dirn = PASSES_DIR * vec
+    spmm = PASSES_SPMM * vec + 12.0 * info["nnz_a"] + 4.0 * (nr + 1) + 4.0 * nr
+    return PASSES_INIT * vec + (K + 1) * fwd + K * (bwd + dirn + spmm)
+
+
+def read_counters():
+    """(fetch_kib, write_kib, copy_factor, digest) from the committed summary."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return (float(vals["fetch_kib_per_dispatch"]), float(vals["write_kib_per_dispatch"]),
+                float(vals["copy_factor"]), vals["kernel_digest"])
+    except KeyError:
+        return None
+
+
+# ----------------------------------------------------------- CPU baseline
+_G = None
+
+
+def _cpu_init(grid):
+    global _G
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1)
+    except Exception:
+        pass
+    _G = (grid, oracle.reduced(oracle.susceptance_full(grid)))
+
+
+def _cpu_one(c):
+    import oracle
+
+    grid, A = _G
+    s = oracle.scenario(grid, int(c), A)
+    return s["status"]
+
+
+def cpu_baseline(grid, seconds: float = 12.0):
+    """The oracle's per-scenario direct solve over a bounded seeded sample,
+    one single-threaded worker per core; run before the GPU is touched."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    _cpu_init(grid)
+    rng = np.random.default_rng(11)
+    probe = rng.choice(grid.m, min(20, grid.m), replace=False)
+    t0 = time.perf_counter()
+    for c in probe:
+        _cpu_one(c)
+    per = (time.perf_counter() - t0) / len(probe)
+    n = int(min(grid.m, max(cores, seconds / per)))
+    sample = rng.choice(grid.m, n, replace=False)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_cpu_init, initargs=(grid,)) as pool:
+        t0 = time.perf_counter()
+        pool.map(_cpu_one, sample, chunksize=max(1, n // (8 * cores)))
+        wall = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / wall, "unit": "scenarios/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded outages of {grid.name} (of {grid.m}), sparse LU + longdouble refinement per "
+                      f"scenario, {cores} single-threaded workers; {wall:.2f} s wall; 1-core {1.0 / per:.1f} "
+                      f"scenarios/s",
+            "cpu_model": model}
+
+
+# ------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid2k", help="grid spec key (grid200, grid2k, grid10k, ...)")
+    ap.add_argument("--block", type=int, default=64, help="scenarios per tile")
+    ap.add_argument("--tol", type=float, default=1e-10, help="relative residual stop")
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--plain-sample", type=int, default=128, help="scenarios timed through the plain PCG")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the scenarios are independent, so more GPUs would each run the "
+              "same kernel on a share of the outage list (see DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import gridgen
+
+    grid = gridgen.make_grid(args.workload)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(grid, args.cpu_seconds)  # before any GPU call
+
+    import torch
+
+    if args.copy_probe:
+        n = 1 << 27  # 1 GiB of float64
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+        return
+
+    import paper_1803_03290_amd as gp
+
+    gp.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=args.block)
+    setup_s = time.perf_counter() - t0
+    info = ctx.info()
+    m = grid.m
+    outages = torch.arange(m, dtype=torch.int32, device=dev)
+    rhs = torch.tensor(grid.P, dtype=torch.float64, device=dev)
+    out = ctx.alloc_outputs(m, flows=True, island=True, resid=True)
+
+    def step():
+        ctx.solve(outages, rhs, tol=args.tol, max_iter=args.max_iter, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+
+    # PCG kernel time per launch, from the library's own events
+    ctx.set_timing(True)
+    kms = []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        kms.append(ctx.pcg_ms())
+    ctx.set_timing(False)
+    torch.cuda.synchronize()
+    pcg_ms = float(np.mean(kms))
+
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    resid = out["resid"].cpu().numpy()
+    S = info["block"]
+    n_tiles = (m + S - 1) // S
+    tile_K = [int(iters[t * S:(t + 1) * S].max()) for t in range(n_tiles)]
+    algo_bytes = float(sum(tile_bytes(info, K, S) for K in tile_K))
+    achieved = algo_bytes / (pcg_ms * 1e-3) / 1e9
+    traffic = None
+    cnt = read_counters()
+    if cnt and cnt[3] == kernel_digest():
+        traffic = (cnt[0] + cnt[1]) * 1024.0 * cnt[2]
+
+    plain = None
+    if not args.no_plain:
+        rng = np.random.default_rng(5)
+        samp = np.sort(rng.choice(m, min(args.plain_sample, m), replace=False)).astype(np.int32)
+        so = torch.tensor(samp, device=dev)
+        pout = ctx.alloc_outputs(len(samp), flows=True, island=True, resid=True)
+        ctx.solve(so, rhs, tol=args.tol, max_iter=args.max_iter, plain=True, out=pout)  # warm-up
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.solve(so, rhs, tol=args.tol, max_iter=args.max_iter, plain=True, out=pout)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        p_ms = e0.elapsed_time(e1)
+        same = float(np.abs(pout["x"].cpu().numpy() - out["x"][so.long()].cpu().numpy()).max())
+        plain = {"value": len(samp) / (p_ms * 1e-3), "unit": "scenarios/s", "scenarios": int(len(samp)),
+                 "ms": p_ms, "max_abs_diff_vs_batched_rad": same,
+                 "note": "seeded sample, one scenario per launch, lanes spread over rows (S=1)"}
+
+    value = m / (ms_step * 1e-3)
+    st_counts = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "scenarios/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{grid.name}: {grid.n}-bus synthetic grid, all {m} N-1 branch outages, batched PCG with "
+                        f"base-case ILU(0), FP64, stop at relative residual {args.tol:g}",
+            "n_bus": grid.n, "n_branches": m, "scenarios": m, "block": S, "tol": args.tol,
+            "grid_sha256": grid.digest()[:16],
+        },
+        "batched_vs_plain": (value / plain["value"]) if plain else None,
+        "plain": plain,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"pcg_tile_kernel<{S}>", "algorithmic_bytes_per_launch": algo_bytes,
+            "avg_launch_ms": pcg_ms, "kernel_digest": kernel_digest(),
+        },
+        "cpu_baseline": cpu,
+        "verify": {
+            "status_counts": st_counts,
+            "max_true_rel_residual": float(resid.max()),
+            "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+            "tile_iters_sum": int(sum(tile_K)), "scenario_iters_sum": int(iters.sum()),
+            "bridges": info["n_bridges"], "setup_s": setup_s, "base_iters": info["base_iters"],
+            "base_resid": info["base_resid"],
+        },
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * gpcg.h - C ABI of the MI355X (gfx950) batched PCG library for "N-1"
+ * contingency screening with a base-case ILU preconditioner
+ * (Zhao, Yuan, Liu, Grinberg, arXiv 1803.03290).
+ *
+ * What the library computes.  For a lossless, tap-free grid with bus 0 as
+ * the slack, the fast-decoupled susceptance system (B' of eq. 4, or B'' of
+ * eq. 5) loses one branch per scenario; Section IV.B notes that only four
+ * entries of the matrix change.  Every scenario is solved by preconditioned
+ * conjugate gradient (Section III) started from the base-case state
+ * (Section III.B, last paragraph) and preconditioned by the incomplete LU
+ * factors of the unmodified base-case matrix (Section IV.B, eqs. 6-7).
+ * Outages that island part of the grid are found by an exact integer bridge
+ * pass; the islanded buses are held at zero and, for B', their power is
+ * re-dispatched proportionally over the remaining main-system generators
+ * (Section IV.C).
+ *
+ * Conventions shared by every entry point.
+ *  - Bus 0 is the slack.  The reduced system drops it: reduced row k is
+ *    bus k + 1, so n_r = n_bus - 1.  Buses are used in the caller's
+ *    numbering; a banded numbering (e.g. reverse Cuthill-McKee) makes the
+ *    ILU(0) preconditioner much stronger.
+ *  - Matrices are CSR with int32 indices, column indices sorted within
+ *    each row, FP64 values.
+ *  - "host" pointers are ordinary CPU memory and are only read during the
+ *    call.  "device" pointers are HIP device memory on the context's GPU
+ *    (for example torch tensors); the library never frees them.
+ *  - Every function returns GPCG_OK (0) or a negative GPCG_E_* code and
+ *    never lets a C++ exception escape; gpcg_last_error() then holds a
+ *    message for the calling thread.
+ *  - Solves are asynchronous on the context's stream: device outputs are
+ *    valid once that stream has been synchronised.
+ *  - A context must not be used by two threads at once; distinct contexts
+ *    are independent.
+ */
+#ifndef GPCG_H
+#define GPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define GPCG_OK 0
+#define GPCG_E_ARG (-1)         /* bad argument: null pointer, size, id out of range */
+#define GPCG_E_HIP (-2)         /* a HIP runtime call failed */
+#define GPCG_E_NOMEM (-3)       /* host or device allocation failed */
+#define GPCG_E_PATTERN (-4)     /* CSR or factor pattern is malformed */
+#define GPCG_E_PIVOT (-5)       /* zero or negative pivot in a factor */
+#define GPCG_E_UNSUPPORTED (-6) /* the grid or block width exceeds a kernel limit */
+
+/* ---- per-scenario outcome (status_out) -------------------------------- */
+#define GPCG_CONVERGED 0           /* ||r|| <= tol ||b|| reached */
+#define GPCG_MAX_ITER 1            /* stopped at max_iter */
+#define GPCG_BREAKDOWN 2           /* p'Ap <= 0: the operator is not positive definite */
+#define GPCG_NONFINITE 3           /* NaN or Inf met (for example in the injections) */
+#define GPCG_CONVERGED_ISLANDED 4  /* converged; part of the grid islanded and was re-dispatched */
+#define GPCG_ISLANDED_NO_GEN 5     /* converged; islanded, but no main-system generator: the slack absorbs */
+#define GPCG_BAD_OUTAGE 6          /* outage id outside [-1, m): nothing solved, outputs zero */
+
+/* ---- system kinds ----------------------------------------------------- */
+#define GPCG_KIND_BP 0  /* B' (P-theta, eq. 4): re-dispatch islanded power, branch flows available */
+#define GPCG_KIND_BPP 1 /* B'' (Q-V, eq. 5): islanded rows zeroed, no re-dispatch, no flows */
+
+typedef struct gpcg_context *gpcg_t;
+
+/* A CSR matrix in host memory. */
+typedef struct {
+    int32_t n;             /* rows (= columns) */
+    int32_t nnz;           /* stored entries */
+    const int32_t *rowptr; /* n + 1 */
+    const int32_t *col;    /* nnz, sorted within each row */
+    const double *val;     /* nnz */
+} gpcg_csr;
+
+/* Solver options (all fields may be zero: then defaults apply). */
+typedef struct {
+    int32_t kind;          /* GPCG_KIND_BP (default) or GPCG_KIND_BPP */
+    int32_t block;         /* scenarios per tile, one of 1,2,4,8,16,32,64; 0 = 64 */
+    int32_t base_max_iter; /* iterations per base-case solve step; 0 = 20000 */
+    int32_t lookahead;     /* rows the triangular-solve scheduler may look ahead; 0 = 256 */
+} gpcg_options;
+
+/* Context facts, for logging and for the roofline accounting. */
+typedef struct {
+    int32_t n_bus, m, n_r;
+    int32_t nnz_a, nnz_l, nnz_u;
+    int32_t bandwidth;  /* max |i - j| over the pattern of A */
+    int32_t block;      /* S: scenarios per tile */
+    int32_t rows_per_step; /* R = 64 / S: rows a wavefront treats per step */
+    int32_t ring_fwd, ring_bwd; /* LDS ring rows of the forward / backward solves */
+    int32_t steps_fwd, steps_bwd; /* schedule steps of the forward / backward solves */
+    int32_t n_bridges;
+    int32_t base_iters; /* PCG iterations spent on the base-case solve (all refinement steps) */
+    double base_resid;  /* relative residual of the base-case state, double-double */
+} gpcg_info;
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char *gpcg_last_error(void);
+
+/* ---- host-side preparation (no GPU involved) --------------------------- */
+
+/*
+ * Reduced susceptance matrix of the grid: sum over branches of
+ * (1/x_e) u_e u_e^T with u_e = e_from - e_to (B' of eq. 4), plus diag(shunt)
+ * when shunt != NULL (B'' of eq. 5, reactor sign), with the slack row and
+ * column dropped.  Parallel branches add up.
+ *   from, to, x: host, m entries; 0 <= from, to < n_bus, from != to, x > 0.
+ *   shunt: host, n_bus entries, or NULL.
+ *   rowptr: host output, n_bus entries (n_r + 1).
+ *   col, val: host outputs with room for cap entries; cap >= n_bus - 1 + 2m
+ *   always suffices.  *nnz_out receives the entry count.
+ */
+int gpcg_assemble(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, const double *x,
+                  const double *shunt, int32_t *rowptr, int32_t *col, double *val, int32_t cap,
+                  int32_t *nnz_out);
+
+/*
+ * Zero-fill incomplete LU of A (Saad, Iterative Methods for Sparse Linear
+ * Systems, Alg. 10.4), the preconditioner of Section IV.B: L strictly lower
+ * with unit diagonal implied, U upper with the diagonal, such that (I+L)U
+ * equals A on the pattern of A.  All pointers are host memory;
+ * l_rowptr / u_rowptr have n + 1 entries, l_col / l_val / u_col / u_val room
+ * for A->nnz entries.  Counts go to *nnz_l, *nnz_u.
+ * Errors: GPCG_E_PATTERN (unsorted row or missing diagonal),
+ * GPCG_E_PIVOT (a zero pivot).
+ */
+int gpcg_ilu0(const gpcg_csr *A, int32_t *l_rowptr, int32_t *l_col, double *l_val, int32_t *nnz_l,
+              int32_t *u_rowptr, int32_t *u_col, double *u_val, int32_t *nnz_u);
+
+/*
+ * Exact integer topology pass (the islanding detection of Section IV.C):
+ * depth-first search from the slack, low-link bridge test keyed by branch
+ * id (so parallel branches are never bridges).  All pointers are host
+ * memory:
+ *   is_bridge: m entries, 1 when removing the branch disconnects the grid;
+ *   pre: n_bus entries, depth-first pre-order number of each bus (slack 0);
+ *   subtree: n_bus entries, size of each bus's DFS subtree;
+ *   island_lo, island_hi: m entries; the buses cut off from the slack by a
+ *     bridge c are exactly those with island_lo[c] <= pre[bus] < island_hi[c]
+ *     (lo == hi == 0 for other branches).
+ * Error GPCG_E_ARG when the grid is not connected.
+ */
+int gpcg_topology(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, uint8_t *is_bridge,
+                  int32_t *pre, int32_t *subtree, int32_t *island_lo, int32_t *island_hi);
+
+/* ---- contexts ------------------------------------------------------------ */
+
+/*
+ * Create a context on the current HIP device: upload the reduced matrix A
+ * (B' or B'') and its factors L (strictly lower, unit diagonal implied) and
+ * U (upper with diagonal) - normally gpcg_ilu0(A), but any factors with the
+ * same shapes are accepted, e.g. an exact LU - plus the branch table, run
+ * the topology pass and the triangular-solve scheduling, and fix the base
+ * state theta_b used as the start of every scenario (Section III.B):
+ *   - theta_base != NULL: host, n_bus entries (slack entry ignored);
+ *   - otherwise theta_b solves A theta = base_rhs on the device by PCG with
+ *     iterative refinement whose residual is formed in double-double.
+ * base_rhs: host, n_bus entries (slack entry ignored); required when
+ * theta_base is NULL, ignored otherwise.
+ * stream: a hipStream_t (NULL = the null stream) on which every later
+ * operation of the context is enqueued.
+ * On error *out is NULL and nothing is leaked.
+ */
+int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, const int32_t *br_to,
+               const double *br_x, const gpcg_csr *A, const gpcg_csr *L, const gpcg_csr *U,
+               const double *base_rhs, const double *theta_base, const gpcg_options *opt, void *stream);
+
+/* Free a context and its device memory (NULL is ignored). */
+void gpcg_destroy(gpcg_t h);
+
+/* Fill *info with the context's sizes and set-up results. */
+int gpcg_get_info(gpcg_t h, gpcg_info *info);
+
+/* Copy the topology pass results into host arrays of m entries (is_bridge)
+ * and n_bus entries (theta_base: the base state, slack entry 0). Either
+ * pointer may be NULL. Synchronises the context's stream. */
+int gpcg_get_base(gpcg_t h, uint8_t *is_bridge, double *theta_base);
+
+/*
+ * Solve n_out outage scenarios (the hot path).  Scenario s takes branch
+ * outages[s] out (-1: no outage, the base case itself).  The scenarios are
+ * batched S to a tile: one wavefront carries S scenario columns through the
+ * whole PCG, so every sweep reads the shared matrix and factor entries once
+ * for S right-hand sides.
+ *
+ *   outages:    device int32[n_out], -1 <= outages[s] < m.
+ *   rhs:        device f64[n_bus]: P for B' (slack entry ignored), or the
+ *               B'' right-hand side.  Scenario s solves
+ *               A_c theta = rhs' on its main rows, where rhs' is rhs after
+ *               re-dispatch (B') or with islanded entries zeroed (B'').
+ *   tol:        stop when ||r_k||_2 <= tol ||rhs'_M||_2 (recursive residual).
+ *   max_iter:   per scenario, >= 1.
+ *   x_out:      device f64[n_out * n_bus], scenario-major: angles (B') or
+ *               magnitude corrections (B''); 0 at the slack and on islands.
+ *   flows_out:  device f64[n_out * m] or NULL; B' only: (theta_from -
+ *               theta_to) / x_e, 0 on the outaged branch and inside islands.
+ *   iters_out:  device int32[n_out]: step-length updates taken.
+ *   status_out: device int32[n_out]: GPCG_CONVERGED ... GPCG_ISLANDED_NO_GEN.
+ *   island_out: device uint8[n_out * n_bus] or NULL: 1 on islanded buses.
+ *   resid_out:  device f64[n_out] or NULL: true relative residual
+ *               ||rhs'_M - A_c theta_M|| / ||rhs'_M|| of the returned
+ *               theta, formed in double-double.
+ * Workspace (5 n_r S doubles per tile) is owned by the context and grows on
+ * demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
+ * max_iter < 1, or flows requested from a B'' context.  Outage ids are read
+ * on the device only: an id outside [-1, m) gives that scenario status
+ * GPCG_BAD_OUTAGE and zero outputs, the other scenarios are unaffected.
+ */
+int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                             int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out,
+                             int32_t *status_out, uint8_t *island_out, double *resid_out);
+
+/*
+ * The same computation with the plain per-scenario PCG: one scenario at a
+ * time (S = 1), each as its own launch in the context's stream, with the
+ * wavefront's 64 lanes spread over rows instead of scenarios.  Same
+ * arguments and results as gpcg_solve_contingencies; this is the baseline
+ * the batched form is measured against.
+ */
+int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                     int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
+                     uint8_t *island_out, double *resid_out);
+
+/*
+ * One outage-corrected sparse matrix product on its own: q = A_c p for
+ * ncols scenario columns, with the outaged branch's coupling removed per
+ * column (the edge "shielding" of the GPCG listing in Section III.B) and
+ * islanded rows zeroed, plus pq[j] = p_j' q_j.  p and q are device f64
+ * blocks in the tile-interleaved layout the solver uses:
+ * element (row i, column j) sits at ((j / S) * n_r + i) * S + j % S with
+ * S = the context's block; ncols must be a multiple of S.
+ * outages: device int32[ncols].  pq: device f64[ncols] or NULL.
+ */
+int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, double *q, double *pq);
+
+/*
+ * Kernel timing.  With timing enabled, every solve records a HIP event on
+ * the context's stream right before its first PCG kernel launch and one
+ * right after its last, so the interval covers the PCG kernel(s) only (not
+ * the base residual or output kernels).  gpcg_get_timing waits for the
+ * second event of the last solve and returns the interval in milliseconds.
+ */
+int gpcg_set_timing(gpcg_t h, int enable);
+int gpcg_get_timing(gpcg_t h, double *pcg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPCG_H */

@@ -1,0 +1,267 @@
+"""ctypes binding of ``libgpcg.so``: same names as the C ABI, marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpcg.so")
+
+CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE, CONVERGED_ISLANDED, ISLANDED_NO_GEN, BAD_OUTAGE = range(7)
+KIND_BP, KIND_BPP = 0, 1
+
+_i32p = C.POINTER(C.c_int32)
+_f64p = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class GpcgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gpcg error {code}: {msg}")
+        self.code = code
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("rowptr", _i32p), ("col", _i32p), ("val", _f64p)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("base_max_iter", C.c_int32), ("lookahead", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("n_bus", C.c_int32), ("m", C.c_int32), ("n_r", C.c_int32),
+        ("nnz_a", C.c_int32), ("nnz_l", C.c_int32), ("nnz_u", C.c_int32),
+        ("bandwidth", C.c_int32), ("block", C.c_int32), ("rows_per_step", C.c_int32),
+        ("ring_fwd", C.c_int32), ("ring_bwd", C.c_int32), ("steps_fwd", C.c_int32), ("steps_bwd", C.c_int32),
+        ("n_bridges", C.c_int32), ("base_iters", C.c_int32), ("base_resid", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# (name, restype, argtypes) of every exported symbol of include/gpcg.h
+_VP = C.c_void_p
+SIGNATURES = {
+    "gpcg_last_error": (C.c_char_p, []),
+    "gpcg_assemble": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, _f64p, C.c_int32,
+                                _i32p]),
+    "gpcg_ilu0": (C.c_int, [C.POINTER(_Csr), _i32p, _i32p, _f64p, _i32p, _i32p, _i32p, _f64p, _i32p]),
+    "gpcg_topology": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _u8p, _i32p, _i32p, _i32p, _i32p]),
+    "gpcg_setup": (C.c_int, [C.POINTER(_VP), C.c_int32, C.c_int32, _i32p, _i32p, _f64p, C.POINTER(_Csr),
+                             C.POINTER(_Csr), C.POINTER(_Csr), _f64p, _f64p, C.POINTER(_Options), _VP]),
+    "gpcg_destroy": (None, [_VP]),
+    "gpcg_get_info": (C.c_int, [_VP, C.POINTER(Info)]),
+    "gpcg_get_base": (C.c_int, [_VP, _u8p, _f64p]),
+    "gpcg_solve_contingencies": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
+                                           _VP, _VP]),
+    "gpcg_solve_plain": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
+    "gpcg_get_timing": (C.c_int, [_VP, _f64p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgpcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1803_03290_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GpcgError(rc, lib().gpcg_last_error().decode())
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(_i32p)
+
+
+def _fp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_f64p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Csr:
+    """Host CSR matrix (int32 indices, float64 values)."""
+
+    def __init__(self, rowptr, col, val):
+        self.rowptr, self.col, self.val = _i32(rowptr), _i32(col), _f64(val)
+        self.n = len(self.rowptr) - 1
+
+    @property
+    def nnz(self):
+        return int(self.rowptr[-1])
+
+    def _c(self):
+        return _Csr(self.n, self.nnz, _ip(self.rowptr), _ip(self.col), _fp(self.val))
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+
+def assemble(n_bus, br_from, br_to, x, shunt=None) -> Csr:
+    """gpcg_assemble: reduced B' (or B'' with shunts), slack row/column dropped."""
+    f, t, xx = _i32(br_from), _i32(br_to), _f64(x)
+    m = len(f)
+    cap = n_bus - 1 + 2 * m
+    rowptr = np.zeros(n_bus, np.int32)
+    col = np.zeros(max(cap, 1), np.int32)
+    val = np.zeros(max(cap, 1), np.float64)
+    nnz = C.c_int32(0)
+    sh = None if shunt is None else _f64(shunt)
+    _check(lib().gpcg_assemble(n_bus, m, _ip(f), _ip(t), _fp(xx), _fp(sh), _ip(rowptr), _ip(col), _fp(val), cap,
+                               C.byref(nnz)))
+    return Csr(rowptr, col[: nnz.value].copy(), val[: nnz.value].copy())
+
+
+def ilu0(A: Csr):
+    """gpcg_ilu0: zero-fill incomplete LU; returns (L strictly lower, U upper)."""
+    n, nnz = A.n, A.nnz
+    lr, ur = np.zeros(n + 1, np.int32), np.zeros(n + 1, np.int32)
+    lc, uc = np.zeros(max(nnz, 1), np.int32), np.zeros(max(nnz, 1), np.int32)
+    lv, uv = np.zeros(max(nnz, 1)), np.zeros(max(nnz, 1))
+    nl, nu = C.c_int32(0), C.c_int32(0)
+    a = A._c()
+    _check(lib().gpcg_ilu0(C.byref(a), _ip(lr), _ip(lc), _fp(lv), C.byref(nl), _ip(ur), _ip(uc), _fp(uv),
+                           C.byref(nu)))
+    return (Csr(lr, lc[: nl.value].copy(), lv[: nl.value].copy()), Csr(ur, uc[: nu.value].copy(), uv[: nu.value].copy()))
+
+
+def topology(n_bus, br_from, br_to):
+    """gpcg_topology: bridge flags, DFS pre-order, subtree sizes, island intervals."""
+    f, t = _i32(br_from), _i32(br_to)
+    m = len(f)
+    isb = np.zeros(m, np.uint8)
+    pre, sub = np.zeros(n_bus, np.int32), np.zeros(n_bus, np.int32)
+    lo, hi = np.zeros(m, np.int32), np.zeros(m, np.int32)
+    _check(lib().gpcg_topology(n_bus, m, _ip(f), _ip(t), isb.ctypes.data_as(_u8p), _ip(pre), _ip(sub), _ip(lo),
+                               _ip(hi)))
+    return dict(is_bridge=isb.astype(bool), pre=pre, subtree=sub, island_lo=lo, island_hi=hi)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A device context (gpcg_setup / gpcg_destroy) for one grid and one
+    matrix kind.  ``A``, ``L``, ``U`` default to the library's own assembly
+    and ILU(0) of the branch table."""
+
+    def __init__(self, n_bus, br_from, br_to, x, base_rhs=None, *, shunt=None, kind=KIND_BP, block=64,
+                 theta_base=None, A: Csr | None = None, L: Csr | None = None, U: Csr | None = None, lookahead=0,
+                 stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP GPU is required")
+        self._lib = lib()
+        self.n_bus, self.m, self.kind = int(n_bus), len(br_from), kind
+        self.br_from, self.br_to, self.x = _i32(br_from), _i32(br_to), _f64(x)
+        self.A = A if A is not None else assemble(n_bus, br_from, br_to, x, shunt)
+        if L is None or U is None:
+            L, U = ilu0(self.A)
+        self.L, self.U = L, U
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        opt = _Options(kind, block, 0, lookahead)
+        a, l, u = self.A._c(), L._c(), U._c()
+        h = C.c_void_p()
+        rhs = None if base_rhs is None else _f64(base_rhs)
+        tb = None if theta_base is None else _f64(theta_base)
+        _check(self._lib.gpcg_setup(C.byref(h), self.n_bus, self.m, _ip(self.br_from), _ip(self.br_to),
+                                    _fp(self.x), C.byref(a), C.byref(l), C.byref(u), _fp(rhs), _fp(tb),
+                                    C.byref(opt), C.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gpcg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        I = Info()
+        _check(self._lib.gpcg_get_info(self._h, C.byref(I)))
+        return I.as_dict()
+
+    def base(self):
+        """(is_bridge[m] bool, theta_base[n_bus]) as NumPy arrays."""
+        isb = np.zeros(self.m, np.uint8)
+        th = np.zeros(self.n_bus)
+        _check(self._lib.gpcg_get_base(self._h, isb.ctypes.data_as(_u8p), _fp(th)))
+        return isb.astype(bool), th
+
+    def alloc_outputs(self, n_out, flows=True, island=True, resid=True, device=None):
+        import torch
+
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        out = dict(
+            x=torch.empty((n_out, self.n_bus), dtype=torch.float64, device=dev),
+            iters=torch.empty(n_out, dtype=torch.int32, device=dev),
+            status=torch.empty(n_out, dtype=torch.int32, device=dev),
+        )
+        out["flows"] = torch.empty((n_out, self.m), dtype=torch.float64, device=dev) if flows else None
+        out["island"] = torch.empty((n_out, self.n_bus), dtype=torch.uint8, device=dev) if island else None
+        out["resid"] = torch.empty(n_out, dtype=torch.float64, device=dev) if resid else None
+        return out
+
+    def solve(self, outages, rhs, tol=1e-12, max_iter=20000, *, plain=False, out=None, flows=None, island=True,
+              resid=True):
+        """gpcg_solve_contingencies (or gpcg_solve_plain): outages and rhs are
+        device tensors (int32[n_out], float64[n_bus]).  Returns the dict of
+        device output tensors x, flows, iters, status, island, resid."""
+        if flows is None:
+            flows = self.kind == KIND_BP
+        n_out = int(outages.shape[0])
+        if out is None:
+            out = self.alloc_outputs(n_out, flows, island, resid, outages.device)
+        fn = self._lib.gpcg_solve_plain if plain else self._lib.gpcg_solve_contingencies
+        _check(fn(self._h, n_out, _ptr(outages), _ptr(rhs), float(tol), int(max_iter), _ptr(out["x"]),
+                  _ptr(out["flows"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["island"]),
+                  _ptr(out["resid"])))
+        return out
+
+    def set_timing(self, enable=True):
+        """gpcg_set_timing: bracket every solve's PCG kernels with HIP events."""
+        _check(self._lib.gpcg_set_timing(self._h, int(bool(enable))))
+
+    def pcg_ms(self) -> float:
+        """gpcg_get_timing: PCG kernel time of the last solve, in ms."""
+        v = C.c_double(0)
+        _check(self._lib.gpcg_get_timing(self._h, C.byref(v)))
+        return v.value
+
+    def spmm(self, outages, p, q, pq=None):
+        """gpcg_spmm on tile-interleaved device blocks."""
+        _check(self._lib.gpcg_spmm(self._h, int(outages.shape[0]), _ptr(outages), _ptr(p), _ptr(q), _ptr(pq)))

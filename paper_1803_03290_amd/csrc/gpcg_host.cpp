@@ -1,0 +1,857 @@
+// Host side of the batched contingency PCG library: the C ABI declared in
+// include/gpcg.h, argument checks, the host preparation passes (matrix
+// assembly, ILU(0), integer topology pass, triangular-solve scheduling) and
+// the device context.
+#include "../../include/gpcg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gpcg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(GPCG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return GPCG_OK;
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return GPCG_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return GPCG_E_ARG;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return GPCG_E_ARG;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR checks
+void check_csr(const gpcg_csr *M, const char *name, int n_expect) {
+    if (!M) fail(GPCG_E_ARG, std::string(name) + " is NULL");
+    if (M->n != n_expect) fail(GPCG_E_ARG, std::string(name) + " has the wrong size");
+    if (M->n < 0 || M->nnz < 0 || (M->n > 0 && (!M->rowptr || (M->nnz > 0 && (!M->col || !M->val)))))
+        fail(GPCG_E_ARG, std::string(name) + ": missing arrays");
+    if (M->n == 0) return;
+    if (M->rowptr[0] != 0 || M->rowptr[M->n] != M->nnz) fail(GPCG_E_PATTERN, std::string(name) + ": bad rowptr");
+    for (int i = 0; i < M->n; ++i) {
+        if (M->rowptr[i + 1] < M->rowptr[i]) fail(GPCG_E_PATTERN, std::string(name) + ": rowptr decreases");
+        for (int e = M->rowptr[i]; e < M->rowptr[i + 1]; ++e) {
+            const int j = M->col[e];
+            if (j < 0 || j >= M->n) fail(GPCG_E_PATTERN, std::string(name) + ": column out of range");
+            if (e > M->rowptr[i] && M->col[e - 1] >= j) fail(GPCG_E_PATTERN, std::string(name) + ": unsorted row");
+            if (!std::isfinite(M->val[e])) fail(GPCG_E_ARG, std::string(name) + ": non-finite value");
+        }
+    }
+}
+
+void check_branches(int n_bus, int m, const int32_t *from, const int32_t *to, const double *x) {
+    if (n_bus < 1 || m < 0) fail(GPCG_E_ARG, "need n_bus >= 1 and m >= 0");
+    if (m > 0 && (!from || !to)) fail(GPCG_E_ARG, "branch endpoints are NULL");
+    for (int e = 0; e < m; ++e) {
+        if (from[e] < 0 || from[e] >= n_bus || to[e] < 0 || to[e] >= n_bus || from[e] == to[e])
+            fail(GPCG_E_ARG, "branch endpoint out of range or a self-loop");
+        if (x && !(x[e] > 0.0 && std::isfinite(x[e]))) fail(GPCG_E_ARG, "branch reactance must be positive and finite");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduced susceptance matrix (slack = bus 0 dropped).
+int assemble(int n_bus, int m, const int32_t *from, const int32_t *to, const double *x, const double *shunt,
+             std::vector<int32_t> &rowptr, std::vector<int32_t> &col, std::vector<double> &val) {
+    const int nr = n_bus - 1;
+    // adjacency of reduced rows with summed susceptances, via per-row buckets
+    std::vector<std::vector<std::pair<int, double>>> rows(nr);
+    std::vector<double> diag(nr, 0.0);
+    for (int e = 0; e < m; ++e) {
+        const double b = 1.0 / x[e];
+        const int f = from[e] - 1, t = to[e] - 1;
+        if (f >= 0) diag[f] += b;
+        if (t >= 0) diag[t] += b;
+        if (f >= 0 && t >= 0) {
+            rows[f].push_back({t, -b});
+            rows[t].push_back({f, -b});
+        }
+    }
+    if (shunt)
+        for (int i = 0; i < nr; ++i) diag[i] += shunt[i + 1];
+    rowptr.assign(nr + 1, 0);
+    col.clear();
+    val.clear();
+    for (int i = 0; i < nr; ++i) {
+        auto &r = rows[i];
+        r.push_back({i, diag[i]});
+        std::sort(r.begin(), r.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        for (size_t k = 0; k < r.size(); ++k) {
+            if (!col.empty() && (int)col.size() > rowptr[i] && col.back() == r[k].first)
+                val.back() += r[k].second;  // parallel branches add up
+            else {
+                col.push_back(r[k].first);
+                val.push_back(r[k].second);
+            }
+        }
+        rowptr[i + 1] = (int32_t)col.size();
+    }
+    return (int)col.size();
+}
+
+// Zero-fill incomplete LU, IKJ order (Saad, Alg. 10.4), with a dense
+// column-to-position map of the current row.
+void ilu0(const gpcg_csr &A, std::vector<double> &F, std::vector<int> &diagpos) {
+    const int n = A.n;
+    F.assign(A.val, A.val + A.nnz);
+    diagpos.assign(n, -1);
+    for (int i = 0; i < n; ++i)
+        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
+            if (A.col[e] == i) diagpos[i] = e;
+    for (int i = 0; i < n; ++i)
+        if (diagpos[i] < 0) fail(GPCG_E_PATTERN, "row " + std::to_string(i) + " has no diagonal entry");
+    std::vector<int> pos(n, -1);
+    for (int i = 0; i < n; ++i) {
+        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) pos[A.col[e]] = e;
+        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+            const int k = A.col[e];
+            if (k >= i) break;
+            const double piv = F[diagpos[k]];
+            if (piv == 0.0) fail(GPCG_E_PIVOT, "zero pivot at row " + std::to_string(k));
+            F[e] /= piv;
+            const double lik = F[e];
+            for (int q = diagpos[k] + 1; q < A.rowptr[k + 1]; ++q) {
+                const int pj = pos[A.col[q]];
+                if (pj >= 0) F[pj] -= lik * F[q];
+            }
+        }
+        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) pos[A.col[e]] = -1;
+    }
+}
+
+// Iterative DFS from the slack with low-link values; the tree edge into v is
+// remembered by branch id so a parallel branch counts as a back edge.
+struct Topology {
+    std::vector<uint8_t> is_bridge;
+    std::vector<int32_t> pre, sub, lo, hi;
+    int n_bridges = 0;
+};
+
+Topology topology(int n_bus, int m, const int32_t *from, const int32_t *to) {
+    Topology T;
+    std::vector<int> adj_ptr(n_bus + 1, 0), adj(2 * (size_t)m), adj_e(2 * (size_t)m);
+    for (int e = 0; e < m; ++e) {
+        adj_ptr[from[e] + 1]++;
+        adj_ptr[to[e] + 1]++;
+    }
+    for (int v = 0; v < n_bus; ++v) adj_ptr[v + 1] += adj_ptr[v];
+    std::vector<int> fill(adj_ptr.begin(), adj_ptr.end() - 1);
+    for (int e = 0; e < m; ++e) {
+        adj[fill[from[e]]] = to[e];
+        adj_e[fill[from[e]]++] = e;
+        adj[fill[to[e]]] = from[e];
+        adj_e[fill[to[e]]++] = e;
+    }
+    T.pre.assign(n_bus, -1);
+    T.sub.assign(n_bus, 1);
+    T.is_bridge.assign(m, 0);
+    T.lo.assign(m, 0);
+    T.hi.assign(m, 0);
+    std::vector<int> low(n_bus), parent_edge(n_bus, -1), it(n_bus), stack;
+    int counter = 0;
+    if (n_bus > 0) {
+        stack.push_back(0);
+        T.pre[0] = low[0] = counter++;
+        it[0] = adj_ptr[0];
+        while (!stack.empty()) {
+            const int v = stack.back();
+            if (it[v] < adj_ptr[v + 1]) {
+                const int k = it[v]++;
+                const int w = adj[k], e = adj_e[k];
+                if (e == parent_edge[v]) continue;
+                if (T.pre[w] < 0) {
+                    T.pre[w] = low[w] = counter++;
+                    parent_edge[w] = e;
+                    it[w] = adj_ptr[w];
+                    stack.push_back(w);
+                } else {
+                    low[v] = std::min(low[v], T.pre[w]);
+                }
+            } else {
+                stack.pop_back();
+                if (!stack.empty()) {
+                    const int u = stack.back();
+                    low[u] = std::min(low[u], low[v]);
+                    T.sub[u] += T.sub[v];
+                    if (low[v] > T.pre[u]) {
+                        const int e = parent_edge[v];
+                        T.is_bridge[e] = 1;
+                        T.lo[e] = T.pre[v];
+                        T.hi[e] = T.pre[v] + T.sub[v];
+                        T.n_bridges++;
+                    }
+                }
+            }
+        }
+    }
+    if (counter != n_bus) fail(GPCG_E_ARG, "the grid is not connected");
+    return T;
+}
+
+// ---------------------------------------------------------------------------
+// Triangular-solve schedule.  deps[i] lists the rows row i needs, all of them
+// "earlier" (smaller index for the forward solve; the backward solve is run
+// on mirrored indices).  Each step takes up to R ready rows, scanning from
+// the lowest unfinished row over a window of `look` rows, so the rows in
+// flight stay close together and a small LDS ring can hold every value that
+// is still to be read.
+struct Schedule {
+    int R = 1, steps = 0, ring = 1;
+    std::vector<int32_t> rows;  // steps x R, -1 = idle
+};
+
+int ring_rows_needed(const std::vector<int32_t> &rows, int R, int n, const std::vector<std::vector<int>> &deps,
+                     int max_ring) {
+    for (int W = 1; W <= max_ring; W <<= 1) {
+        std::vector<int> owner(W, -1);
+        bool ok = true;
+        const int steps = (int)rows.size() / R;
+        for (int s = 0; s < steps && ok; ++s) {
+            for (int k = 0; k < R && ok; ++k) {
+                const int i = rows[(size_t)s * R + k];
+                if (i < 0) continue;
+                for (int j : deps[i])
+                    if (owner[j & (W - 1)] != j) ok = false;
+            }
+            for (int k = 0; k < R && ok; ++k) {
+                const int i = rows[(size_t)s * R + k];
+                if (i < 0) continue;
+                for (int k2 = 0; k2 < k; ++k2) {
+                    const int i2 = rows[(size_t)s * R + k2];
+                    if (i2 >= 0 && ((i2 ^ i) & (W - 1)) == 0) ok = false;
+                }
+            }
+            for (int k = 0; k < R && ok; ++k) {
+                const int i = rows[(size_t)s * R + k];
+                if (i >= 0) owner[i & (W - 1)] = i;
+            }
+        }
+        if (ok) return W;
+    }
+    return -1;
+}
+
+Schedule build_schedule(int n, int R, int look, const std::vector<std::vector<int>> &deps) {
+    Schedule S;
+    S.R = R;
+    std::vector<int> done_step(n, -1);
+    int lowest = 0, processed = 0, step = 0;
+    std::vector<int> pick;
+    while (processed < n) {
+        pick.clear();
+        const int end = std::min(n, lowest + std::max(look, R));
+        for (int i = lowest; i < end && (int)pick.size() < R; ++i) {
+            if (done_step[i] >= 0) continue;
+            bool ready = true;
+            for (int j : deps[i])
+                if (done_step[j] < 0) {
+                    ready = false;
+                    break;
+                }
+            if (ready) pick.push_back(i);
+        }
+        if (pick.empty()) fail(GPCG_E_PATTERN, "triangular factor has a dependency cycle");
+        for (int i : pick) done_step[i] = step;
+        for (int k = 0; k < R; ++k) S.rows.push_back(k < (int)pick.size() ? pick[k] : -1);
+        processed += (int)pick.size();
+        while (lowest < n && done_step[lowest] >= 0) ++lowest;
+        ++step;
+    }
+    S.steps = step;
+    return S;
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t count) {
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+        n = count;
+        if (count == 0) return;
+        if (hipMalloc((void **)&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            n = 0;
+            fail(GPCG_E_NOMEM, "device allocation failed");
+        }
+    }
+    void upload(const T *src, size_t count, hipStream_t st) {
+        alloc(count);
+        if (count) hip_check(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, st), "upload");
+    }
+};
+
+struct DevSchedule {
+    int R = 1, steps_f = 0, steps_b = 0, ring_f = 1, ring_b = 1;
+    DevBuf<int32_t> f, b;
+};
+
+}  // namespace
+
+struct gpcg_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_bus = 0, m = 0, n_r = 0, kind = GPCG_KIND_BP, S = 64, look = 256, bandwidth = 0;
+    int nnz_a = 0, nnz_l = 0, nnz_u = 0;
+    DevBuf<int32_t> a_rowptr, a_col, l_rowptr, l_col, u_rowptr, u_col;
+    DevBuf<double> a_val, l_val, u_val, u_invdiag;
+    DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
+    DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
+    DevBuf<double> ws, gfac, partial;
+    std::vector<std::vector<int>> deps_f, deps_b;  // for schedule building
+    std::unique_ptr<DevSchedule> sched_batched, sched_plain;
+    Topology topo;
+    std::vector<double> theta_b_host;
+    int base_iters = 0;
+    double base_resid = 0.0;
+    bool timing = false, timed = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    ~gpcg_context() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+
+    DevSchedule &schedule_for(int S_) {
+        const int R = gpcg::kWave / S_;
+        std::unique_ptr<DevSchedule> &slot = (S_ == 1) ? sched_plain : sched_batched;
+        if (slot && slot->R == R) return *slot;
+        auto D = std::make_unique<DevSchedule>();
+        D->R = R;
+        const int max_ring = std::max(1, gpcg::kLdsBudget / (int)(S_ * sizeof(double)));
+        for (int look_try = look;; look_try /= 2) {
+            Schedule F = build_schedule(n_r, R, look_try, deps_f);
+            Schedule B = build_schedule(n_r, R, look_try, deps_b);
+            // the backward schedule was built on mirrored indices
+            for (auto &v : B.rows)
+                if (v >= 0) v = n_r - 1 - v;
+            std::vector<std::vector<int>> deps_b_real(n_r);
+            for (int i = 0; i < n_r; ++i)
+                for (int j : deps_b[i]) deps_b_real[n_r - 1 - i].push_back(n_r - 1 - j);
+            const int wf = ring_rows_needed(F.rows, R, n_r, deps_f, max_ring);
+            const int wb = ring_rows_needed(B.rows, R, n_r, deps_b_real, max_ring);
+            if (wf > 0 && wb > 0) {
+                D->steps_f = F.steps;
+                D->steps_b = B.steps;
+                D->ring_f = wf;
+                D->ring_b = wb;
+                D->f.upload(F.rows.data(), F.rows.size(), stream);
+                D->b.upload(B.rows.data(), B.rows.size(), stream);
+                hip_check(hipStreamSynchronize(stream), "schedule upload");
+                break;
+            }
+            if (look_try <= R)
+                fail(GPCG_E_UNSUPPORTED, "the factors' bandwidth needs a larger LDS ring than a wavefront may use; "
+                                         "number the buses in a banded order (e.g. reverse Cuthill-McKee)");
+        }
+        slot = std::move(D);
+        return *slot;
+    }
+
+    gpcg::PcgParams params(const DevSchedule &D, const int32_t *outages, int n_out, const double *rhs, double tol,
+                           int max_iter, int32_t *iters, int32_t *status) {
+        gpcg::PcgParams p{};
+        p.n_r = n_r;
+        p.n_bus = n_bus;
+        p.m = m;
+        p.kind = kind;
+        p.a_rowptr = a_rowptr.p;
+        p.a_col = a_col.p;
+        p.a_val = a_val.p;
+        p.l_rowptr = l_rowptr.p;
+        p.l_col = l_col.p;
+        p.l_val = l_val.p;
+        p.u_rowptr = u_rowptr.p;
+        p.u_col = u_col.p;
+        p.u_val = u_val.p;
+        p.u_invdiag = u_invdiag.p;
+        p.br_from = br_from.p;
+        p.br_to = br_to.p;
+        p.br_b = br_b.p;
+        p.pre_row = pre_row.p;
+        p.isl_lo = isl_lo.p;
+        p.isl_hi = isl_hi.p;
+        p.sched_f = D.f.p;
+        p.sched_b = D.b.p;
+        p.steps_f = D.steps_f;
+        p.steps_b = D.steps_b;
+        p.wmask_f = D.ring_f - 1;
+        p.wmask_b = D.ring_b - 1;
+        p.theta_b = theta_b.p;
+        p.rho_b = rho_b.p;
+        p.rhs = rhs;
+        p.outages = outages;
+        p.n_out = n_out;
+        p.tile0 = 0;
+        p.tol2 = tol * tol;
+        p.max_iter = max_iter;
+        p.ws = ws.p;
+        p.iters_out = iters;
+        p.status_out = status;
+        p.gfac_out = gfac.p;
+        return p;
+    }
+
+    void ensure_workspace(int n_out, int S_) {
+        const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
+        const size_t need = tiles * gpcg::kVectors * (size_t)n_r * S_;
+        if (ws.n < need) ws.alloc(need);
+        if (gfac.n < (size_t)std::max(n_out, 1)) gfac.alloc(std::max(n_out, 1));
+    }
+};
+
+namespace {
+
+void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const double *rhs, double tol,
+               int max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
+               uint8_t *island_out, double *resid_out) {
+    if (!h) fail(GPCG_E_ARG, "context is NULL");
+    if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
+    if (n_out == 0) return;
+    if (!outages || !rhs || !x_out || !iters_out || !status_out) fail(GPCG_E_ARG, "a required pointer is NULL");
+    if (max_iter < 1) fail(GPCG_E_ARG, "max_iter must be >= 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) fail(GPCG_E_ARG, "tol must be finite and >= 0");
+    if (flows_out && h->kind != GPCG_KIND_BP) fail(GPCG_E_ARG, "flows are only defined for a B' context");
+    hip_check(hipSetDevice(h->device), "hipSetDevice");
+    DevSchedule &D = h->schedule_for(S_);
+    h->ensure_workspace(n_out, S_);
+    // residual of the base state for this right-hand side, in double-double
+    hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
+                                         h->rho_b.p, h->stream),
+              "base residual");
+    gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
+    const int ring = std::max(D.ring_f, D.ring_b);
+    const int n_tiles = (n_out + S_ - 1) / S_;
+    if (h->timing) hip_check(hipEventRecord(h->ev0, h->stream), "event");
+    if (S_ == 1) {
+        // plain: one scenario per launch, one after the other
+        for (int t = 0; t < n_tiles; ++t) {
+            p.tile0 = t;
+            hip_check(gpcg::launch_pcg(p, 1, 1, ring, h->stream), "pcg launch");
+        }
+    } else {
+        hip_check(gpcg::launch_pcg(p, S_, n_tiles, ring, h->stream), "pcg launch");
+    }
+    if (h->timing) {
+        hip_check(hipEventRecord(h->ev1, h->stream), "event");
+        h->timed = true;
+    }
+    gpcg::OutParams o{};
+    o.n_r = h->n_r;
+    o.n_bus = h->n_bus;
+    o.m = h->m;
+    o.kind = h->kind;
+    o.S = S_;
+    o.n_out = n_out;
+    o.a_rowptr = h->a_rowptr.p;
+    o.a_col = h->a_col.p;
+    o.a_val = h->a_val.p;
+    o.br_from = h->br_from.p;
+    o.br_to = h->br_to.p;
+    o.br_x = h->br_x.p;
+    o.br_b = h->br_b.p;
+    o.pre_bus = h->pre_bus.p;
+    o.isl_lo = h->isl_lo.p;
+    o.isl_hi = h->isl_hi.p;
+    o.theta_b = h->theta_b.p;
+    o.rhs = rhs;
+    o.outages = outages;
+    o.ws = h->ws.p;
+    o.status = status_out;
+    o.gfac = h->gfac.p;
+    o.x_out = x_out;
+    o.flows_out = flows_out;
+    o.resid_out = resid_out;
+    o.island_out = island_out;
+    hip_check(gpcg::launch_outputs(o, h->stream), "output launch");
+}
+
+// Base state: theta_b solves A theta = rhs.  PCG in correction form from the
+// current theta_b (outage -1, so r0 is the double-double residual), then
+// theta_b += delta; repeated while the residual keeps shrinking.
+void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
+    const int n_bus = h->n_bus;
+    DevBuf<double> rhs;
+    rhs.upload(rhs_host, n_bus, h->stream);
+    DevBuf<int32_t> out1;
+    const int32_t minus1 = -1;
+    out1.upload(&minus1, 1, h->stream);
+    DevBuf<int32_t> it, st;
+    it.alloc(1);
+    st.alloc(1);
+    DevBuf<double> dsum;
+    dsum.alloc(2);
+    std::vector<double> zero(n_bus, 0.0);
+    h->theta_b.upload(zero.data(), n_bus, h->stream);
+    DevSchedule &D = h->schedule_for(1);
+    h->ensure_workspace(1, 1);
+    double bnorm2 = 0.0;
+    hip_check(gpcg::launch_sumsq(n_bus - 1, rhs.p + 1, dsum.p + 1, h->stream), "sumsq");
+    hip_check(hipMemcpyAsync(&bnorm2, dsum.p + 1, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    double prev = INFINITY;
+    h->base_iters = 0;
+    for (int pass = 0; pass < 6; ++pass) {
+        hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs.p,
+                                             h->rho_b.p, h->stream),
+                  "base residual");
+        double rr = 0.0;
+        hip_check(gpcg::launch_sumsq(h->n_r, h->rho_b.p, dsum.p, h->stream), "sumsq");
+        hip_check(hipMemcpyAsync(&rr, dsum.p, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const double rel = bnorm2 > 0.0 ? std::sqrt(rr / bnorm2) : std::sqrt(rr);
+        h->base_resid = rel;
+        if (!(rel < prev * 0.5) || rel < 1e-16) break;
+        prev = rel;
+        gpcg::PcgParams p = h->params(D, out1.p, 1, rhs.p, 1e-13, max_iter, it.p, st.p);
+        const int ring = std::max(D.ring_f, D.ring_b);
+        hip_check(gpcg::launch_pcg(p, 1, 1, ring, h->stream), "base pcg");
+        hip_check(gpcg::launch_base_accumulate(h->n_r, h->theta_b.p, h->ws.p, h->stream), "base accumulate");
+        int its = 0;
+        hip_check(hipMemcpyAsync(&its, it.p, sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        h->base_iters += its;
+    }
+    h->theta_b_host.assign(n_bus, 0.0);
+    hip_check(hipMemcpyAsync(h->theta_b_host.data(), h->theta_b.p, n_bus * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream),
+              "copy");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *gpcg_last_error(void) { return g_last_error.c_str(); }
+
+int gpcg_assemble(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, const double *x,
+                  const double *shunt, int32_t *rowptr, int32_t *col, double *val, int32_t cap, int32_t *nnz_out) {
+    return guarded([&] {
+        if (!x || !rowptr || !col || !val || !nnz_out) fail(GPCG_E_ARG, "NULL argument");
+        check_branches(n_bus, m, from, to, x);
+        std::vector<int32_t> rp, c;
+        std::vector<double> v;
+        const int nnz = assemble(n_bus, m, from, to, x, shunt, rp, c, v);
+        if (nnz > cap) fail(GPCG_E_ARG, "output capacity too small");
+        std::copy(rp.begin(), rp.end(), rowptr);
+        std::copy(c.begin(), c.end(), col);
+        std::copy(v.begin(), v.end(), val);
+        *nnz_out = nnz;
+    });
+}
+
+int gpcg_ilu0(const gpcg_csr *A, int32_t *l_rowptr, int32_t *l_col, double *l_val, int32_t *nnz_l,
+              int32_t *u_rowptr, int32_t *u_col, double *u_val, int32_t *nnz_u) {
+    return guarded([&] {
+        if (!A || !l_rowptr || !l_col || !l_val || !nnz_l || !u_rowptr || !u_col || !u_val || !nnz_u)
+            fail(GPCG_E_ARG, "NULL argument");
+        check_csr(A, "A", A->n);
+        std::vector<double> F;
+        std::vector<int> dp;
+        ilu0(*A, F, dp);
+        int nl = 0, nu = 0;
+        l_rowptr[0] = u_rowptr[0] = 0;
+        for (int i = 0; i < A->n; ++i) {
+            for (int e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+                if (A->col[e] < i) {
+                    l_col[nl] = A->col[e];
+                    l_val[nl++] = F[e];
+                } else {
+                    u_col[nu] = A->col[e];
+                    u_val[nu++] = F[e];
+                }
+            }
+            l_rowptr[i + 1] = nl;
+            u_rowptr[i + 1] = nu;
+        }
+        *nnz_l = nl;
+        *nnz_u = nu;
+    });
+}
+
+int gpcg_topology(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, uint8_t *is_bridge,
+                  int32_t *pre, int32_t *subtree, int32_t *island_lo, int32_t *island_hi) {
+    return guarded([&] {
+        check_branches(n_bus, m, from, to, nullptr);
+        Topology T = topology(n_bus, m, from, to);
+        if (is_bridge) std::copy(T.is_bridge.begin(), T.is_bridge.end(), is_bridge);
+        if (pre) std::copy(T.pre.begin(), T.pre.end(), pre);
+        if (subtree) std::copy(T.sub.begin(), T.sub.end(), subtree);
+        if (island_lo) std::copy(T.lo.begin(), T.lo.end(), island_lo);
+        if (island_hi) std::copy(T.hi.begin(), T.hi.end(), island_hi);
+    });
+}
+
+int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, const int32_t *br_to,
+               const double *br_x, const gpcg_csr *A, const gpcg_csr *L, const gpcg_csr *U, const double *base_rhs,
+               const double *theta_base, const gpcg_options *opt, void *stream) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) fail(GPCG_E_ARG, "out is NULL");
+        if (n_bus < 2) fail(GPCG_E_ARG, "need at least two buses");
+        if (!br_x) fail(GPCG_E_ARG, "br_x is NULL");
+        check_branches(n_bus, m, br_from, br_to, br_x);
+        const int nr = n_bus - 1;
+        check_csr(A, "A", nr);
+        check_csr(L, "L", nr);
+        check_csr(U, "U", nr);
+        if (!theta_base && !base_rhs) fail(GPCG_E_ARG, "either base_rhs or theta_base is required");
+        gpcg_options o{};
+        if (opt) o = *opt;
+        if (o.kind != GPCG_KIND_BP && o.kind != GPCG_KIND_BPP) fail(GPCG_E_ARG, "unknown kind");
+        const int S = o.block ? o.block : 64;
+        if (S < 1 || S > 64 || (S & (S - 1))) fail(GPCG_E_ARG, "block must be a power of two in [1, 64]");
+        // factor shapes: L strictly lower, U upper with a positive diagonal first
+        std::vector<double> invdiag(nr);
+        std::vector<int32_t> us_rowptr(nr + 1, 0), us_col;
+        std::vector<double> us_val;
+        for (int i = 0; i < nr; ++i) {
+            for (int e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e)
+                if (L->col[e] >= i) fail(GPCG_E_PATTERN, "L must be strictly lower triangular");
+            if (U->rowptr[i + 1] == U->rowptr[i] || U->col[U->rowptr[i]] != i)
+                fail(GPCG_E_PATTERN, "U must hold the diagonal as the first entry of each row");
+            const double d = U->val[U->rowptr[i]];
+            if (!(d > 0.0)) fail(GPCG_E_PIVOT, "U has a zero or negative pivot at row " + std::to_string(i));
+            invdiag[i] = 1.0 / d;
+            for (int e = U->rowptr[i] + 1; e < U->rowptr[i + 1]; ++e) {
+                us_col.push_back(U->col[e]);
+                us_val.push_back(U->val[e]);
+            }
+            us_rowptr[i + 1] = (int32_t)us_col.size();
+        }
+        bool has_diag = true;
+        int bw = 0;
+        for (int i = 0; i < nr; ++i) {
+            bool d = false;
+            for (int e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+                d |= A->col[e] == i;
+                bw = std::max(bw, std::abs(A->col[e] - i));
+            }
+            has_diag &= d;
+        }
+        if (!has_diag) fail(GPCG_E_PATTERN, "A lacks a diagonal entry");
+
+        auto h = std::make_unique<gpcg_context>();
+        hip_check(hipGetDevice(&h->device), "hipGetDevice");
+        h->stream = (hipStream_t)stream;
+        h->n_bus = n_bus;
+        h->m = m;
+        h->n_r = nr;
+        h->kind = o.kind;
+        h->S = S;
+        h->look = o.lookahead > 0 ? o.lookahead : 256;
+        h->bandwidth = bw;
+        h->nnz_a = A->nnz;
+        h->nnz_l = L->nnz;
+        h->nnz_u = U->nnz;
+        h->topo = topology(n_bus, m, br_from, br_to);
+        // dependency lists for the schedules (backward on mirrored indices)
+        h->deps_f.assign(nr, {});
+        h->deps_b.assign(nr, {});
+        for (int i = 0; i < nr; ++i) {
+            for (int e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) h->deps_f[i].push_back(L->col[e]);
+            for (int e = us_rowptr[i]; e < us_rowptr[i + 1]; ++e) h->deps_b[nr - 1 - i].push_back(nr - 1 - us_col[e]);
+        }
+        hipStream_t st = h->stream;
+        h->a_rowptr.upload(A->rowptr, nr + 1, st);
+        h->a_col.upload(A->col, A->nnz, st);
+        h->a_val.upload(A->val, A->nnz, st);
+        h->l_rowptr.upload(L->rowptr, nr + 1, st);
+        h->l_col.upload(L->col, L->nnz, st);
+        h->l_val.upload(L->val, L->nnz, st);
+        h->u_rowptr.upload(us_rowptr.data(), nr + 1, st);
+        h->u_col.upload(us_col.data(), us_col.size(), st);
+        h->u_val.upload(us_val.data(), us_val.size(), st);
+        h->u_invdiag.upload(invdiag.data(), nr, st);
+        std::vector<double> b(m);
+        for (int e = 0; e < m; ++e) b[e] = 1.0 / br_x[e];
+        h->br_from.upload(br_from, m, st);
+        h->br_to.upload(br_to, m, st);
+        h->br_x.upload(br_x, m, st);
+        h->br_b.upload(b.data(), m, st);
+        std::vector<int32_t> prerow(nr);
+        for (int i = 0; i < nr; ++i) prerow[i] = h->topo.pre[i + 1];
+        h->pre_row.upload(prerow.data(), nr, st);
+        h->pre_bus.upload(h->topo.pre.data(), n_bus, st);
+        h->isl_lo.upload(h->topo.lo.data(), m, st);
+        h->isl_hi.upload(h->topo.hi.data(), m, st);
+        h->rho_b.alloc(nr);
+        hip_check(hipStreamSynchronize(st), "setup upload");
+        h->schedule_for(S);
+        if (theta_base) {
+            std::vector<double> t(theta_base, theta_base + n_bus);
+            t[0] = 0.0;
+            h->theta_b.upload(t.data(), n_bus, st);
+            h->theta_b_host = t;
+            hip_check(hipStreamSynchronize(st), "theta upload");
+        } else {
+            base_solve(h.get(), base_rhs, o.base_max_iter > 0 ? o.base_max_iter : 20000);
+        }
+        *out = h.release();
+    });
+}
+
+void gpcg_destroy(gpcg_t h) {
+    if (!h) return;
+    try {
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        delete h;
+    } catch (...) {
+    }
+}
+
+int gpcg_get_info(gpcg_t h, gpcg_info *info) {
+    return guarded([&] {
+        if (!h || !info) fail(GPCG_E_ARG, "NULL argument");
+        DevSchedule &D = h->schedule_for(h->S);
+        gpcg_info I{};
+        I.n_bus = h->n_bus;
+        I.m = h->m;
+        I.n_r = h->n_r;
+        I.nnz_a = h->nnz_a;
+        I.nnz_l = h->nnz_l;
+        I.nnz_u = h->nnz_u;
+        I.bandwidth = h->bandwidth;
+        I.block = h->S;
+        I.rows_per_step = D.R;
+        I.ring_fwd = D.ring_f;
+        I.ring_bwd = D.ring_b;
+        I.steps_fwd = D.steps_f;
+        I.steps_bwd = D.steps_b;
+        I.n_bridges = h->topo.n_bridges;
+        I.base_iters = h->base_iters;
+        I.base_resid = h->base_resid;
+        *info = I;
+    });
+}
+
+int gpcg_get_base(gpcg_t h, uint8_t *is_bridge, double *theta_base) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "NULL context");
+        if (is_bridge) std::copy(h->topo.is_bridge.begin(), h->topo.is_bridge.end(), is_bridge);
+        if (theta_base) std::copy(h->theta_b_host.begin(), h->theta_b_host.end(), theta_base);
+    });
+}
+
+int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                             int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out,
+                             int32_t *status_out, uint8_t *island_out, double *resid_out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        run_solve(h, h->S, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
+                  resid_out);
+    });
+}
+
+int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                     int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
+                     uint8_t *island_out, double *resid_out) {
+    return guarded([&] {
+        run_solve(h, 1, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
+                  resid_out);
+    });
+}
+
+int gpcg_set_timing(gpcg_t h, int enable) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "NULL context");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        if (enable && !h->ev0) {
+            hip_check(hipEventCreate(&h->ev0), "hipEventCreate");
+            hip_check(hipEventCreate(&h->ev1), "hipEventCreate");
+        }
+        h->timing = enable != 0;
+        h->timed = false;
+    });
+}
+
+int gpcg_get_timing(gpcg_t h, double *pcg_ms) {
+    return guarded([&] {
+        if (!h || !pcg_ms) fail(GPCG_E_ARG, "NULL argument");
+        if (!h->timed) fail(GPCG_E_ARG, "no timed solve yet (enable timing first)");
+        hip_check(hipEventSynchronize(h->ev1), "hipEventSynchronize");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1), "hipEventElapsedTime");
+        *pcg_ms = ms;
+    });
+}
+
+int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, double *q, double *pq) {
+    return guarded([&] {
+        if (!h || !outages || !p || !q) fail(GPCG_E_ARG, "NULL argument");
+        if (ncols <= 0 || ncols % h->S) fail(GPCG_E_ARG, "ncols must be a positive multiple of the block");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        gpcg::SpmmParams s{};
+        s.n_r = h->n_r;
+        s.m = h->m;
+        s.ncols = ncols;
+        s.a_rowptr = h->a_rowptr.p;
+        s.a_col = h->a_col.p;
+        s.a_val = h->a_val.p;
+        s.br_from = h->br_from.p;
+        s.br_to = h->br_to.p;
+        s.br_b = h->br_b.p;
+        s.pre_row = h->pre_row.p;
+        s.isl_lo = h->isl_lo.p;
+        s.isl_hi = h->isl_hi.p;
+        s.outages = outages;
+        s.p = p;
+        s.q = q;
+        s.pq = pq;
+        double *partial = nullptr;
+        if (pq) {
+            const size_t need = (size_t)gpcg::spmm_chunks(h->n_r) * ncols;
+            if (h->partial.n < need) h->partial.alloc(need);
+            partial = h->partial.p;
+        }
+        hip_check(gpcg::launch_spmm_partial(s, h->S, partial, h->stream), "spmm launch");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+"""GPU parity tests: the device library (through its C ABI) against the oracle.
+
+Bars (written here, derived in the design doc):
+  * angles: |theta_gpu - theta_oracle|_inf <= 1e-8 rad;
+  * flows:  |f_gpu - f_oracle| * x_e <= 2e-8;
+  * island flags, bridge flags and scenario status: bit-exact;
+  * iterations: within +-1 of the oracle's textbook PCG on the same
+    numbering and factors;
+  * true relative residual (double-double) <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ANGLE_TOL = 1e-8
+FLOW_TOL = 2e-8
+RESID_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_03290_amd as gp
+
+    gp.lib()
+    return gp
+
+
+def _ctx(gp, g, block=64, kind=0, shunt=None, rhs=None):
+    base = g.P if rhs is None else rhs
+    return gp.Context(g.n, g.br_from, g.br_to, g.x, base, block=block, kind=kind, shunt=shunt)
+
+
+def _run(gp, ctx, g, outages, rhs=None, tol=1e-12, max_iter=20000, plain=False):
+    rhs = g.P if rhs is None else rhs
+    o = torch.tensor(np.asarray(outages, np.int32), device="cuda")
+    r = torch.tensor(np.asarray(rhs, np.float64), device="cuda")
+    out = ctx.solve(o, r, tol=tol, max_iter=max_iter, plain=plain, flows=ctx.kind == 0)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+
+
+def _check_against_direct(g, A, outages, res, angle_tol=ANGLE_TOL, rhs=None, redispatch=True, shunt=None):
+    for s, c in enumerate(outages):
+        d = oracle.scenario(g, int(c), A, rhs=rhs, redispatch_islands=redispatch, shunt=shunt)
+        err = np.abs(res["x"][s] - d["theta"]).max()
+        assert err <= angle_tol, (s, c, err)
+        np.testing.assert_array_equal(res["island"][s].astype(bool), d["island"], err_msg=f"outage {c}")
+        assert res["status"][s] == d["status"], (c, res["status"][s], d["status"])
+        if res.get("flows") is not None:
+            ferr = np.abs(res["flows"][s] - d["flows"]) * g.x
+            assert ferr.max() <= FLOW_TOL, (c, ferr.max())
+        assert res["resid"][s] <= RESID_TOL, (c, res["resid"][s])
+
+
+# ------------------------------------------------------------ hand grids
+
+
+@pytest.mark.parametrize("name", gridgen.HAND_GRIDS)
+@pytest.mark.parametrize("block", [64, 1])
+def test_hand_grids(gp, name, block):
+    g = gridgen.hand_grid(name)
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=block)
+    outs = list(range(-1, g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res, angle_tol=1e-12)
+
+
+def test_hand_grid_plain_equals_batched(gp):
+    g = gridgen.hand_grid("two_rings")
+    ctx = _ctx(gp, g, block=8)
+    outs = list(range(-1, g.m))
+    a = _run(gp, ctx, g, outs)
+    b = _run(gp, ctx, g, outs, plain=True)
+    np.testing.assert_allclose(a["x"], b["x"], rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(a["status"], b["status"])
+
+
+# ------------------------------------------------------- 200-bus grid
+
+
+@pytest.mark.parametrize("block", [64, 16, 4, 1])
+def test_grid200_all_outages(gp, grids, block):
+    g = grids["grid200"]
+    thb, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=block)
+    isb, thb_dev = ctx.base()
+    np.testing.assert_array_equal(isb, [oracle.is_bridge(g, c) for c in range(g.m)])
+    np.testing.assert_allclose(thb_dev, thb, rtol=1e-12, atol=1e-13)
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res)
+
+
+def test_grid200_iterations_match_textbook_pcg(gp, grids):
+    g = grids["grid200"]
+    thb, A = oracle.base_case(g)
+    L, U = oracle.ilu0(A)
+    ctx = _ctx(gp, g, block=64)
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs, tol=1e-12)
+    for s, c in enumerate(outs):
+        p = oracle.scenario_pcg(g, c, A, L, U, thb, tol=1e-12)
+        assert abs(int(res["iters"][s]) - p["iters"]) <= 1, (c, res["iters"][s], p["iters"])
+
+
+def test_grid200_plain_matches_batched(gp, grids):
+    g = grids["grid200"]
+    ctx = _ctx(gp, g, block=32)
+    outs = list(range(0, g.m, 5))
+    a = _run(gp, ctx, g, outs)
+    b = _run(gp, ctx, g, outs, plain=True)
+    np.testing.assert_allclose(a["x"], b["x"], rtol=0, atol=1e-10)
+    assert np.all(np.abs(a["iters"] - b["iters"]) <= 1)
+    np.testing.assert_array_equal(a["status"], b["status"])
+
+
+# ------------------------------------------------------- edge cases
+
+
+def test_edge_cases(gp, grids):
+    g = grids["grid200"]
+    thb, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=64)
+    # empty batch
+    res = _run(gp, ctx, g, [])
+    assert res["x"].shape == (0, g.n)
+    # base case, a bad id, a ragged tail of 70 (not a multiple of 64)
+    outs = [-1, g.m, -7] + list(range(67))
+    res = _run(gp, ctx, g, outs)
+    assert res["iters"][0] == 0 and res["status"][0] == 0
+    np.testing.assert_allclose(res["x"][0], thb, rtol=1e-12, atol=1e-13)
+    for s in (1, 2):
+        assert res["status"][s] == gp.BAD_OUTAGE
+        assert np.all(res["x"][s] == 0) and np.all(res["flows"][s] == 0)
+    _check_against_direct(g, A, outs[3:], {k: (v[3:] if v is not None else None) for k, v in res.items()})
+    # max_iter reached
+    res = _run(gp, ctx, g, [5, 6], tol=0.0, max_iter=3)
+    assert np.all(res["status"] == gp.MAX_ITER) and np.all(res["iters"] == 3)
+    # non-finite injections
+    P = g.P.copy()
+    P[7] = np.nan
+    res = _run(gp, ctx, g, [5, 6], rhs=P)
+    assert np.all(res["status"] == gp.NONFINITE)
+
+
+def test_determinism(gp, grids):
+    g = grids["grid2k"]
+    ctx = _ctx(gp, g, block=64)
+    outs = list(range(0, g.m, 11))
+    a = _run(gp, ctx, g, outs)
+    b = _run(gp, ctx, g, outs)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["iters"], b["iters"])
+
+
+def test_spmm_against_numpy(gp, grids):
+    g = grids["grid2k"]
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=64)
+    nr, S = g.n - 1, 64
+    rng = np.random.default_rng(0)
+    outs = rng.integers(-1, g.m, 128).astype(np.int32)
+    P = rng.normal(size=(128, nr))
+    # zero islanded entries as the solver keeps them
+    masks = [~oracle.island_of(g, int(c))[1:] for c in outs]
+    P = P * np.array(masks)
+    tiles = P.reshape(2, S, nr).transpose(0, 2, 1).copy()
+    p = torch.tensor(tiles, device="cuda")
+    q = torch.empty_like(p)
+    pq = torch.empty(128, dtype=torch.float64, device="cuda")
+    ctx.spmm(torch.tensor(outs, device="cuda"), p, q, pq)
+    torch.cuda.synchronize()
+    qh = q.cpu().numpy().transpose(0, 2, 1).reshape(128, nr)
+    for k, c in enumerate(outs):
+        Ac = oracle.outage_matrix(g, A, int(c))
+        expect = np.where(masks[k], Ac @ P[k], 0.0)
+        np.testing.assert_allclose(qh[k], expect, rtol=1e-13, atol=1e-9)
+        assert pq[k].item() == pytest.approx(P[k] @ expect, rel=1e-11)
+
+
+# ---------------------------------------------------- 2,000-bus grid
+
+
+def test_grid2k_all_outages_batched(gp, grids):
+    """The benchmark workload at its full size and launch configuration:
+    every island flag checked bit-exact, angles and flows on a seeded sample
+    of 120 outages, iterations on 12."""
+    g = grids["grid2k"]
+    thb, A = oracle.base_case(g)
+    L, U = oracle.ilu0(A)
+    ctx = _ctx(gp, g, block=64)
+    outs = np.arange(g.m)
+    res = _run(gp, ctx, g, outs)
+    isb, _ = ctx.base()
+    for c in outs:
+        np.testing.assert_array_equal(res["island"][c].astype(bool), oracle.island_of(g, int(c)))
+    assert res["resid"].max() <= RESID_TOL
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(g.m, 120, replace=False))
+    _check_against_direct(g, A, sample, {k: (v[sample] if v is not None else None) for k, v in res.items()})
+    for c in sample[:12]:
+        p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=1e-12)
+        assert abs(int(res["iters"][c]) - p["iters"]) <= 1, (c, res["iters"][c], p["iters"])
+
+
+# --------------------------------------------------------- B'' context
+
+
+def test_bpp_context(gp, grids):
+    g = grids["grid200"]
+    bsh = np.random.default_rng(3).uniform(0, 0.05, g.n)
+    Q = np.random.default_rng(4).normal(0, 0.2, g.n)
+    _, A = oracle.base_case(g, rhs=Q, shunt=bsh)
+    ctx = _ctx(gp, g, block=16, kind=1, shunt=bsh, rhs=Q)
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs, rhs=Q)
+    for s, c in enumerate(outs):
+        d = oracle.scenario(g, c, A, rhs=Q, redispatch_islands=False, shunt=bsh)
+        assert np.abs(res["x"][s] - d["theta"]).max() <= ANGLE_TOL
+        np.testing.assert_array_equal(res["island"][s].astype(bool), d["island"])
+        exp = 0 if not d["island"].any() else gp.CONVERGED_ISLANDED
+        assert res["status"][s] == exp

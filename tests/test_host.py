@@ -1,0 +1,109 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host passes (assembly, ILU(0), integer topology) agree with the
+oracle and with brute force.  No GPU call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+import paper_1803_03290_amd as gp
+from paper_1803_03290_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "gpcg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpcg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gp.lib()
+    names = _declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in binding.SIGNATURES, n
+
+
+@pytest.mark.parametrize("key", ["grid200", "grid2k"])
+def test_assembly_matches_oracle(grids, key):
+    g = grids[key]
+    A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
+    Ao = oracle.reduced(oracle.susceptance_full(g))
+    assert (A != 0).nnz == (Ao != 0).nnz
+    np.testing.assert_array_equal(A.indptr, Ao.indptr)
+    np.testing.assert_array_equal(A.indices, Ao.indices)
+    np.testing.assert_allclose(A.data, Ao.data, rtol=1e-15)
+
+
+def test_assembly_with_shunts(grids):
+    g = grids["grid200"]
+    bsh = np.linspace(0.0, 0.05, g.n)
+    A = gp.assemble(g.n, g.br_from, g.br_to, g.x, bsh).to_scipy()
+    Ao = oracle.reduced(oracle.susceptance_full(g, bsh))
+    np.testing.assert_allclose(A.toarray(), Ao.toarray(), rtol=1e-15, atol=0)
+
+
+def test_assembly_parallel_branches():
+    g = gridgen.hand_grid("parallel")
+    A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
+    Ao = oracle.reduced(oracle.susceptance_full(g))
+    np.testing.assert_allclose(A.toarray(), Ao.toarray(), rtol=1e-15)
+
+
+@pytest.mark.parametrize("key", ["grid200", "grid2k"])
+def test_ilu0_matches_oracle(grids, key):
+    g = grids[key]
+    Ah = gp.assemble(g.n, g.br_from, g.br_to, g.x)
+    L, U = gp.ilu0(Ah)
+    Lo, Uo = oracle.ilu0(Ah.to_scipy())
+    np.testing.assert_array_equal(L.rowptr, Lo.indptr)
+    np.testing.assert_array_equal(U.col, Uo.indices)
+    np.testing.assert_allclose(L.val, Lo.data, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(U.val, Uo.data, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", gridgen.HAND_GRIDS)
+def test_topology_hand_grids(name):
+    g = gridgen.hand_grid(name)
+    T = gp.topology(g.n, g.br_from, g.br_to)
+    for c in range(g.m):
+        isl = oracle.island_of(g, c)
+        assert T["is_bridge"][c] == oracle.is_bridge(g, c)
+        got = (T["pre"] >= T["island_lo"][c]) & (T["pre"] < T["island_hi"][c])
+        np.testing.assert_array_equal(got, isl)
+
+
+@pytest.mark.parametrize("key", ["grid200", "grid2k"])
+def test_topology_bit_exact_against_brute_force(grids, key):
+    g = grids[key]
+    T = gp.topology(g.n, g.br_from, g.br_to)
+    assert T["pre"][0] == 0 and T["subtree"][0] == g.n
+    assert sorted(T["pre"].tolist()) == list(range(g.n))
+    step = 1 if g.n <= 200 else 7
+    for c in range(0, g.m, step):
+        isl = oracle.island_of(g, c)
+        assert bool(T["is_bridge"][c]) == bool(isl.any())
+        got = (T["pre"] >= T["island_lo"][c]) & (T["pre"] < T["island_hi"][c])
+        np.testing.assert_array_equal(got, isl)
+
+
+def test_errors_are_reported():
+    with pytest.raises(gp.GpcgError) as e:
+        gp.assemble(3, [0, 1], [1, 5], [0.1, 0.1])
+    assert e.value.code == -1 and "range" in str(e.value)
+    with pytest.raises(gp.GpcgError) as e:
+        gp.topology(4, [0, 2], [1, 3])
+    assert e.value.code == -1 and "connected" in str(e.value)
+    A = binding.Csr([0, 1, 2], [1, 0], [1.0, 1.0])  # no diagonal
+    with pytest.raises(gp.GpcgError) as e:
+        gp.ilu0(A)
+    assert e.value.code == -4
+    with pytest.raises(gp.GpcgError) as e:
+        gp.assemble(3, [0, 1], [1, 2], [0.1, -0.1])
+    assert e.value.code == -1
