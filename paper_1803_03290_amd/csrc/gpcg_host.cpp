@@ -233,37 +233,6 @@ struct Schedule {
     std::vector<int32_t> rows;  // steps x R, -1 = idle
 };
 
-int ring_rows_needed(const std::vector<int32_t> &rows, int R, int n, const std::vector<std::vector<int>> &deps,
-                     int max_ring) {
-    for (int W = 1; W <= max_ring; W <<= 1) {
-        std::vector<int> owner(W, -1);
-        bool ok = true;
-        const int steps = (int)rows.size() / R;
-        for (int s = 0; s < steps && ok; ++s) {
-            for (int k = 0; k < R && ok; ++k) {
-                const int i = rows[(size_t)s * R + k];
-                if (i < 0) continue;
-                for (int j : deps[i])
-                    if (owner[j & (W - 1)] != j) ok = false;
-            }
-            for (int k = 0; k < R && ok; ++k) {
-                const int i = rows[(size_t)s * R + k];
-                if (i < 0) continue;
-                for (int k2 = 0; k2 < k; ++k2) {
-                    const int i2 = rows[(size_t)s * R + k2];
-                    if (i2 >= 0 && ((i2 ^ i) & (W - 1)) == 0) ok = false;
-                }
-            }
-            for (int k = 0; k < R && ok; ++k) {
-                const int i = rows[(size_t)s * R + k];
-                if (i >= 0) owner[i & (W - 1)] = i;
-            }
-        }
-        if (ok) return W;
-    }
-    return -1;
-}
-
 Schedule build_schedule(int n, int R, int look, const std::vector<std::vector<int>> &deps) {
     Schedule S;
     S.R = R;
@@ -324,9 +293,204 @@ struct DevBuf {
     }
 };
 
+// Host copy of a CSR matrix (the context keeps A, L and strict-upper U).
+struct CsrH {
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> val;
+    int len(int i) const { return rowptr[i + 1] - rowptr[i]; }
+};
+
+// A sweep program in host memory (see gpcg::Program).
+struct HostProg {
+    int steps = 0, ring = 1;
+    std::vector<int32_t> rec;  // 4 per (step, slot)
+    std::vector<int32_t> ent;  // 3 per (step, entry, slot)
+    std::vector<double> dinv;  // per (step, slot), backward only
+};
+
+// One slot of a step before packing.
+struct Slot {
+    int row = -1;    // row finished here (-1 none)
+    int la = -1;     // product: look-ahead row whose direction is updated
+    bool cont = false;
+    int seg_begin = 0, seg_end = 0;  // entries [begin, end) of the row `src`
+    int src = -1;                    // row whose entries this slot multiplies
+};
+
+using Steps = std::vector<std::vector<Slot>>;
+
+// Split every row of a step list into segments of at most K entries: the
+// continuation segments go to extra steps placed right before the step,
+// in the same slot.  Look-ahead updates move to the first of those steps.
+Steps expand(const Steps &in, int R, int K, const CsrH &T) {
+    Steps out;
+    for (const auto &st : in) {
+        int extra = 0;
+        for (const Slot &sl : st)
+            if (sl.row >= 0) extra = std::max(extra, (std::max(T.len(sl.row), 1) + K - 1) / K - 1);
+        for (int c = 0; c <= extra; ++c) {
+            std::vector<Slot> o(R);
+            for (int k = 0; k < R; ++k) {
+                const Slot &sl = st[k];
+                if (c == 0) o[k].la = sl.la;
+                if (sl.row < 0) continue;
+                const int nseg = std::max(1, (T.len(sl.row) + K - 1) / K);
+                const int first = extra - (nseg - 1);  // step of the row's first segment
+                if (c < first) continue;
+                const int seg = c - first;
+                o[k].src = sl.row;
+                o[k].seg_begin = seg * K;
+                o[k].seg_end = std::min(T.len(sl.row), seg * K + K);
+                if (c == extra)
+                    o[k].row = sl.row;
+                else
+                    o[k].cont = true;
+            }
+            out.push_back(std::move(o));
+        }
+    }
+    return out;
+}
+
+// Smallest power-of-two ring that keeps every value a step reads: each step
+// first writes its look-ahead rows (product), then reads the columns of its
+// entries, then writes the rows it finishes (triangular solves).
+int ring_needed(const Steps &st, const CsrH &T, bool tri, int max_ring) {
+    for (int W = 1; W <= max_ring; W <<= 1) {
+        std::vector<int> owner(W, -1);
+        bool ok = true;
+        for (const auto &step : st) {
+            for (const Slot &sl : step)
+                if (sl.la >= 0) owner[sl.la & (W - 1)] = sl.la;
+            for (size_t a = 0; a < step.size() && ok; ++a)
+                for (size_t b = 0; b < a && ok; ++b) {
+                    if (step[a].la >= 0 && step[b].la >= 0 && ((step[a].la ^ step[b].la) & (W - 1)) == 0) ok = false;
+                    if (tri && step[a].row >= 0 && step[b].row >= 0 && ((step[a].row ^ step[b].row) & (W - 1)) == 0)
+                        ok = false;
+                }
+            for (const Slot &sl : step) {
+                if (sl.src < 0) continue;
+                for (int e = T.rowptr[sl.src] + sl.seg_begin; e < T.rowptr[sl.src] + sl.seg_end; ++e)
+                    if (owner[T.col[e] & (W - 1)] != T.col[e]) ok = false;
+                if (!tri && sl.row >= 0 && owner[sl.row & (W - 1)] != sl.row) ok = false;  // p_i read for p'q
+            }
+            if (tri)
+                for (const Slot &sl : step)
+                    if (sl.row >= 0) owner[sl.row & (W - 1)] = sl.row;
+            if (!ok) break;
+        }
+        if (ok) return W;
+    }
+    return -1;
+}
+
+void put_entry(std::vector<int32_t> &ent, double v, int lds) {
+    int32_t w[2];
+    std::memcpy(w, &v, sizeof v);
+    ent.push_back(w[0]);
+    ent.push_back(w[1]);
+    ent.push_back(lds);
+}
+
+// Pack an expanded step list for the kernel (see gpcg::Program).
+HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, bool tri,
+              const std::vector<double> *invdiag, const std::vector<int32_t> &prerow) {
+    HostProg H;
+    H.ring = ring;
+    H.steps = (int)st.size();
+    const int zero = ring * S * 8, trash = (ring + 1) * S * 8;
+    Steps all = st;  // plus idle steps that the kernel's prefetch may read past the end
+    all.insert(all.end(), gpcg::kPadSteps, std::vector<Slot>(R));
+    for (const auto &step : all) {
+        for (int k = 0; k < R; ++k) {
+            const Slot &sl = step[k];
+            H.rec.push_back(sl.row);
+            if (sl.row >= 0)
+                H.rec.push_back((sl.row & (ring - 1)) * S * 8);
+            else
+                H.rec.push_back(tri ? trash : zero);
+            if (tri) {
+                H.rec.push_back(sl.row >= 0 ? prerow[sl.row] : -1);
+                H.rec.push_back(sl.cont ? 1 : (sl.row >= 0 ? 0 : -1));
+            } else {
+                H.rec.push_back(sl.cont ? -2 : (sl.row >= 0 ? prerow[sl.row] : -1));
+                H.rec.push_back(sl.la);
+            }
+            if (invdiag) H.dinv.push_back(sl.row >= 0 ? (*invdiag)[sl.row] : 0.0);
+        }
+        for (int j = 0; j < K; ++j)
+            for (int k = 0; k < R; ++k) {
+                const Slot &sl = step[k];
+                if (sl.src >= 0 && sl.seg_begin + j < sl.seg_end) {
+                    const int e = T.rowptr[sl.src] + sl.seg_begin + j;
+                    put_entry(H.ent, T.val[e], (T.col[e] & (ring - 1)) * S * 8);
+                } else {
+                    put_entry(H.ent, 0.0, zero);
+                }
+            }
+    }
+    return H;
+}
+
+// Step list of a triangular solve from its schedule (rows per step).
+Steps tri_steps(const std::vector<int32_t> &sched, int R) {
+    Steps st(sched.size() / R, std::vector<Slot>(R));
+    for (size_t s = 0; s < st.size(); ++s)
+        for (int k = 0; k < R; ++k) {
+            const int row = sched[s * R + k];
+            st[s][k].row = row;
+            st[s][k].src = row;
+            st[s][k].seg_begin = 0;
+            st[s][k].seg_end = 0;  // set by expand()
+        }
+    return st;
+}
+
+// Step list of the product sweep: step c holds rows c R .. c R + R - 1 and
+// updates the direction of rows (c + lead) R ..; `lead` prologue steps come
+// first.
+Steps prod_steps(int nr, int R, int lead) {
+    const int chunks = (nr + R - 1) / R;
+    Steps st;
+    for (int c = -lead; c < chunks; ++c) {
+        std::vector<Slot> step(R);
+        for (int k = 0; k < R; ++k) {
+            const int la = (c + lead) * R + k;
+            step[k].la = (c + lead < chunks && la < nr) ? la : -1;
+            const int row = c * R + k;
+            step[k].row = (c >= 0 && row < nr) ? row : -1;
+        }
+        st.push_back(std::move(step));
+    }
+    return st;
+}
+
+struct DevProgram {
+    int steps = 0, ring = 1;
+    DevBuf<int32_t> rec, ent;
+    DevBuf<double> dinv;
+    void upload(const HostProg &H, hipStream_t st) {
+        steps = H.steps;
+        ring = H.ring;
+        rec.upload(H.rec.data(), H.rec.size(), st);
+        ent.upload(H.ent.data(), H.ent.size(), st);
+        dinv.upload(H.dinv.data(), H.dinv.size(), st);
+    }
+    gpcg::Program view() const {
+        gpcg::Program g{};
+        g.rec = (const int4 *)rec.p;
+        g.ent = (const int3 *)ent.p;
+        g.dinv = dinv.p;
+        g.steps = steps;
+        g.ring = ring;
+        return g;
+    }
+};
+
 struct DevSchedule {
-    int R = 1, steps_f = 0, steps_b = 0, ring_f = 1, ring_b = 1;
-    DevBuf<int32_t> f, b;
+    int R = 1;
+    DevProgram f, b, p;
+    int ring_max() const { return std::max(f.ring, std::max(b.ring, p.ring)); }
 };
 
 }  // namespace
@@ -342,6 +506,9 @@ struct gpcg_context {
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
     std::vector<std::vector<int>> deps_f, deps_b;  // for schedule building
+    CsrH hA, hL, hU;                               // A, L, strict upper of U
+    std::vector<double> h_invdiag;
+    std::vector<int32_t> h_prerow;
     std::unique_ptr<DevSchedule> sched_batched, sched_plain;
     Topology topo;
     std::vector<double> theta_b_host;
@@ -361,25 +528,29 @@ struct gpcg_context {
         if (slot && slot->R == R) return *slot;
         auto D = std::make_unique<DevSchedule>();
         D->R = R;
-        const int max_ring = std::max(1, gpcg::kLdsBudget / (int)(S_ * sizeof(double)));
+        // ring rows + the zero row + the trash row must fit the LDS budget
+        const int max_ring = std::max(1, gpcg::kLdsBudget / (int)(S_ * sizeof(double)) - 2);
+        const int lead = (bandwidth + R - 1) / R;
+        const Steps P = expand(prod_steps(n_r, R, lead), R, gpcg::kEntProd, hA);
+        const int wp = ring_needed(P, hA, false, max_ring);
+        if (wp < 0)
+            fail(GPCG_E_UNSUPPORTED, "the matrix bandwidth needs a larger LDS ring than a wavefront may use; "
+                                     "number the buses in a banded order (e.g. reverse Cuthill-McKee) or use a "
+                                     "smaller block");
         for (int look_try = look;; look_try /= 2) {
             Schedule F = build_schedule(n_r, R, look_try, deps_f);
             Schedule B = build_schedule(n_r, R, look_try, deps_b);
             // the backward schedule was built on mirrored indices
             for (auto &v : B.rows)
                 if (v >= 0) v = n_r - 1 - v;
-            std::vector<std::vector<int>> deps_b_real(n_r);
-            for (int i = 0; i < n_r; ++i)
-                for (int j : deps_b[i]) deps_b_real[n_r - 1 - i].push_back(n_r - 1 - j);
-            const int wf = ring_rows_needed(F.rows, R, n_r, deps_f, max_ring);
-            const int wb = ring_rows_needed(B.rows, R, n_r, deps_b_real, max_ring);
+            const Steps FS = expand(tri_steps(F.rows, R), R, gpcg::kEntTri, hL);
+            const Steps BS = expand(tri_steps(B.rows, R), R, gpcg::kEntTri, hU);
+            const int wf = ring_needed(FS, hL, true, max_ring);
+            const int wb = ring_needed(BS, hU, true, max_ring);
             if (wf > 0 && wb > 0) {
-                D->steps_f = F.steps;
-                D->steps_b = B.steps;
-                D->ring_f = wf;
-                D->ring_b = wb;
-                D->f.upload(F.rows.data(), F.rows.size(), stream);
-                D->b.upload(B.rows.data(), B.rows.size(), stream);
+                D->f.upload(pack(FS, R, S_, wf, gpcg::kEntTri, hL, true, nullptr, h_prerow), stream);
+                D->b.upload(pack(BS, R, S_, wb, gpcg::kEntTri, hU, true, &h_invdiag, h_prerow), stream);
+                D->p.upload(pack(P, R, S_, wp, gpcg::kEntProd, hA, false, nullptr, h_prerow), stream);
                 hip_check(hipStreamSynchronize(stream), "schedule upload");
                 break;
             }
@@ -398,28 +569,15 @@ struct gpcg_context {
         p.n_bus = n_bus;
         p.m = m;
         p.kind = kind;
-        p.a_rowptr = a_rowptr.p;
-        p.a_col = a_col.p;
-        p.a_val = a_val.p;
-        p.l_rowptr = l_rowptr.p;
-        p.l_col = l_col.p;
-        p.l_val = l_val.p;
-        p.u_rowptr = u_rowptr.p;
-        p.u_col = u_col.p;
-        p.u_val = u_val.p;
-        p.u_invdiag = u_invdiag.p;
+        p.fwd = D.f.view();
+        p.bwd = D.b.view();
+        p.prod = D.p.view();
         p.br_from = br_from.p;
         p.br_to = br_to.p;
         p.br_b = br_b.p;
         p.pre_row = pre_row.p;
         p.isl_lo = isl_lo.p;
         p.isl_hi = isl_hi.p;
-        p.sched_f = D.f.p;
-        p.sched_b = D.b.p;
-        p.steps_f = D.steps_f;
-        p.steps_b = D.steps_b;
-        p.wmask_f = D.ring_f - 1;
-        p.wmask_b = D.ring_b - 1;
         p.theta_b = theta_b.p;
         p.rho_b = rho_b.p;
         p.rhs = rhs;
@@ -437,7 +595,7 @@ struct gpcg_context {
 
     void ensure_workspace(int n_out, int S_) {
         const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
-        const size_t need = tiles * gpcg::kVectors * (size_t)n_r * S_;
+        const size_t need = tiles * gpcg::kVectors * (size_t)(n_r + 1) * S_;
         if (ws.n < need) ws.alloc(need);
         if (gfac.n < (size_t)std::max(n_out, 1)) gfac.alloc(std::max(n_out, 1));
     }
@@ -463,7 +621,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
                                          h->rho_b.p, h->stream),
               "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
-    const int ring = std::max(D.ring_f, D.ring_b);
+    const int ring = D.ring_max();
     const int n_tiles = (n_out + S_ - 1) / S_;
     if (h->timing) hip_check(hipEventRecord(h->ev0, h->stream), "event");
     if (S_ == 1) {
@@ -547,8 +705,7 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
         if (!(rel < prev * 0.5) || rel < 1e-16) break;
         prev = rel;
         gpcg::PcgParams p = h->params(D, out1.p, 1, rhs.p, 1e-13, max_iter, it.p, st.p);
-        const int ring = std::max(D.ring_f, D.ring_b);
-        hip_check(gpcg::launch_pcg(p, 1, 1, ring, h->stream), "base pcg");
+        hip_check(gpcg::launch_pcg(p, 1, 1, D.ring_max(), h->stream), "base pcg");
         hip_check(gpcg::launch_base_accumulate(h->n_r, h->theta_b.p, h->ws.p, h->stream), "base accumulate");
         int its = 0;
         hip_check(hipMemcpyAsync(&its, it.p, sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy");
@@ -697,6 +854,18 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
             for (int e = L->rowptr[i]; e < L->rowptr[i + 1]; ++e) h->deps_f[i].push_back(L->col[e]);
             for (int e = us_rowptr[i]; e < us_rowptr[i + 1]; ++e) h->deps_b[nr - 1 - i].push_back(nr - 1 - us_col[e]);
         }
+        h->hA.rowptr.assign(A->rowptr, A->rowptr + nr + 1);
+        h->hA.col.assign(A->col, A->col + A->nnz);
+        h->hA.val.assign(A->val, A->val + A->nnz);
+        h->hL.rowptr.assign(L->rowptr, L->rowptr + nr + 1);
+        h->hL.col.assign(L->col, L->col + L->nnz);
+        h->hL.val.assign(L->val, L->val + L->nnz);
+        h->hU.rowptr = us_rowptr;
+        h->hU.col = us_col;
+        h->hU.val = us_val;
+        h->h_invdiag = invdiag;
+        h->h_prerow.resize(nr);
+        for (int i = 0; i < nr; ++i) h->h_prerow[i] = h->topo.pre[i + 1];
         hipStream_t st = h->stream;
         h->a_rowptr.upload(A->rowptr, nr + 1, st);
         h->a_col.upload(A->col, A->nnz, st);
@@ -760,10 +929,10 @@ int gpcg_get_info(gpcg_t h, gpcg_info *info) {
         I.bandwidth = h->bandwidth;
         I.block = h->S;
         I.rows_per_step = D.R;
-        I.ring_fwd = D.ring_f;
-        I.ring_bwd = D.ring_b;
-        I.steps_fwd = D.steps_f;
-        I.steps_bwd = D.steps_b;
+        I.ring_fwd = D.f.ring;
+        I.ring_bwd = D.b.ring;
+        I.steps_fwd = D.f.steps;
+        I.steps_bwd = D.b.steps;
         I.n_bridges = h->topo.n_bridges;
         I.base_iters = h->base_iters;
         I.base_resid = h->base_resid;

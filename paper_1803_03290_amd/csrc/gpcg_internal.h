@@ -8,8 +8,8 @@
 namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
-constexpr int kVectors = 5;   // per tile: delta, r, p, q, y/z
-constexpr int kLdsBudget = 64 * 1024;  // bytes of ring per wavefront (two waves fit one CU)
+constexpr int kVectors = 5;   // per tile and row: delta, r, p, q, y/z (interleaved per row)
+constexpr int kLdsBudget = 80 * 1024;  // bytes of LDS ring per wavefront (two waves fit one CU)
 
 enum Status : int32_t {
     kConverged = 0,
@@ -21,29 +21,48 @@ enum Status : int32_t {
     kBadOutage = 6,
 };
 
+// Matrix entries per row slot of a step: triangular solves and the product.
+// Longer rows are split on the host into continuation segments placed in
+// the same slot of the steps just before the row's own step; the lane
+// carries their partial sums.
+constexpr int kPadSteps = 32;  // idle steps appended to every program (>= the deepest prefetch)
+constexpr int kEntTri = 4;
+constexpr int kEntProd = 6;
+
+// A sweep program: the steps one wavefront walks, R row slots per step, each
+// slot with a fixed number K of packed matrix entries (padding entries carry
+// value 0 and point at the ring's zero row).
+//   rec[s * R + rs] = {row, own, pre, aux}:
+//     row: the row finished in this slot (-1: idle or continuation segment);
+//     own: LDS byte offset of that row's ring slot for column 0 (the trash
+//          row when row is -1; the zero row for idle product slots);
+//     pre: pre-order number of the row's bus (-1 when none; -2 marks a
+//          continuation segment of the product);
+//     aux: triangular solves: 1 for a continuation segment, else 0 (-1 idle);
+//          product: the look-ahead row whose direction is updated, or -1.
+//   ent[(s * K + j) * R + rs] = {value lo, value hi, LDS byte offset of the
+//     column's ring slot for column 0};
+//   dinv[s * R + rs] = 1 / U_ii (backward solve only).
+struct Program {
+    const int4 *rec;
+    const int3 *ent;
+    const double *dinv;
+    int steps, ring;
+};
+
 // Everything one launch of the tile kernel needs.  All pointers are device
 // memory.  Reduced row i is bus i + 1.
 struct PcgParams {
     int n_r, n_bus, m, kind;
-    // base matrix A (reduced, CSR)
-    const int32_t *a_rowptr, *a_col;
-    const double *a_val;
-    // strictly lower factor L (unit diagonal implied)
-    const int32_t *l_rowptr, *l_col;
-    const double *l_val;
-    // strictly upper part of U, and 1 / diag(U)
-    const int32_t *u_rowptr, *u_col;
-    const double *u_val, *u_invdiag;
+    Program fwd;   // y = L^-1 r  (rows in a dependency-respecting order)
+    Program bwd;   // z = U^-1 y
+    Program prod;  // p = z + beta p, delta += alpha p_old, q = A_c p (natural order, R rows per step)
     // branch table; br_b = 1 / x
     const int32_t *br_from, *br_to;
     const double *br_b;
     // DFS pre-order number of the bus of each reduced row; island interval per branch
     const int32_t *pre_row;
     const int32_t *isl_lo, *isl_hi;
-    // triangular-solve schedules: steps x R row ids (-1 = idle slot)
-    const int32_t *sched_f, *sched_b;
-    int steps_f, steps_b;
-    int wmask_f, wmask_b;  // ring rows - 1 (ring rows are a power of two)
     // base state and its double-double residual for this right-hand side
     const double *theta_b;  // n_bus, slack 0
     const double *rho_b;    // n_r: rhs - A theta_b
@@ -54,7 +73,7 @@ struct PcgParams {
     int tile0;  // first tile of this launch (plain mode launches one tile at a time)
     double tol2;
     int max_iter;
-    double *ws;  // tiles x kVectors x n_r x S
+    double *ws;  // tiles x (n_r + 1) rows x kVectors x S
     int32_t *iters_out, *status_out;
     double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
 };

@@ -3,15 +3,13 @@
 // Layout.  Scenarios are grouped S to a tile; one wavefront owns one tile and
 // carries it through the whole preconditioned CG of Section III.A.  Its 64
 // lanes are R x S with R = 64 / S: lane = rs * S + sc treats scenario column
-// sc and row slot rs.  Every per-scenario vector of a tile is stored
-// row-interleaved, element (row i, column sc) at i * S + sc, so one row of S
-// columns is S contiguous doubles: a wave touching a row for all its columns
-// issues one contiguous S * 8-byte access, and every CSR / factor entry it
-// reads is shared by the S columns.
-//
-// Per tile the workspace holds five vectors: delta (the change of state
-// from the base case), r, p, q = A_c p, and y / z (the forward-solve result,
-// overwritten by the backward-solve result).
+// sc and row slot rs.  Per tile the workspace holds five vectors: delta (the
+// change of state from the base case), r, p, q = A_c p, and y / z (the
+// forward-solve result, overwritten by the backward-solve result).  They are
+// interleaved per row: element (row i, vector v, column sc) at
+// (i * 5 + v) * S + sc, so a wave touching a row reads S contiguous doubles
+// per vector, all five vectors of a row lie together, and every matrix entry
+// it reads is shared by the S columns.
 //
 // The outage of branch c = (f, t) is applied as a rank-1 correction of the
 // shared base matrix: A_c = A - b_c u u^T with u = e_f - e_t (Section IV.B:
@@ -62,8 +60,275 @@ __device__ __forceinline__ void dd_fma(double &hi, double &lo, double a, double 
 }
 
 // ---------------------------------------------------------------------------
-// The tile kernel: init, then PCG iterations until every column stops.
+// Sweeps.  Each sweep walks its program step by step through a three-stage
+// register pipeline: a step's row record is loaded H = 2D steps ahead, its
+// vector rows D steps ahead and its matrix entries E = 2 steps ahead (they
+// are shared by every wave and sit in L1/L2).  A step first consumes its
+// pipeline slots and then refills them with later steps, so no register is
+// copied, no load waits on another load still in flight, and a step only
+// waits on the LDS ring that carries the dependencies between rows.
+// Vector-memory counters complete in order, so the loop has no branches
+// around loads and stores: idle slots read and write the tile's scratch row
+// (row n_r) and the ring's trash row, and padding entries are real zero
+// entries in memory.
+//
+// A tile stores its five vectors interleaved per row: element (row i,
+// vector v, column sc) at (i * 5 + v) * S + sc, so one address per step
+// reaches every vector of a row with immediate offsets.
+enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
+constexpr int kEntAhead = 2;
+
+// The step index as a vector register the compiler cannot see through.
+// Without it a wave-uniform index makes the loaded row id uniform too, and
+// the compiler copies it to a scalar register right after the load, which
+// waits for every load in flight.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ double ring_at(const double *ring, int byte_off) {
+    return *(const double *)((const char *)ring + byte_off);
+}
+
+__device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
+    *(double *)((char *)ring + byte_off) = v;
+}
+
+template <int K>
+struct Ents {
+    int3 e[K];
+};
+
+template <int S, int K>
+__device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, int rs) {
+    constexpr int R = kWave / S;
+    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
+    const int3 *base = g.ent + ((size_t)ss * K) * R + rs;
+#pragma unroll
+    for (int j = 0; j < K; ++j) E.e[j] = base[j * R];
+}
+
+// sum_j v_j * ring[col_j] for the lane's column (lane_off = sc * 8)
+template <int K>
+__device__ __forceinline__ double ring_dot(const Ents<K> &E, const double *ring, int lane_off) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc += __hiloint2double(E.e[j].y, E.e[j].x) * ring_at(ring, E.e[j].z + lane_off);
+    return acc;
+}
+
+struct Tile {
+    double *base;  // row 0, vector 0, column 0 of the tile
+    int nr;
+};
+
 template <int S>
+__device__ __forceinline__ double *row_ptr(const Tile &T, int row, int sc) {
+    return T.base + ((size_t)(row >= 0 ? row : T.nr) * kVectors) * S + sc;
+}
+
+// Programs end with kPadSteps idle steps, so reading past the last real step
+// only needs a clamp (no branch that would wait for the load).
+template <int S>
+__device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
+    constexpr int R = kWave / S;
+    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
+    return g.rec[ss * R + rs];
+}
+
+// ---- forward: r -= alpha q, ||r||^2, y = L^-1 r ---------------------------
+struct FwdVec {
+    double r, q;
+};
+
+template <int S>
+__device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
+    const double *p = row_ptr<S>(T, h.x, sc);
+    v.r = p[VR * S];
+    v.q = p[VQ * S];
+}
+
+template <int S, int D>
+__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                            double alpha) {
+    constexpr int H = 2 * D, E = kEntAhead;
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rr = 0.0, carry = 0.0;
+    int4 hq[H];
+    FwdVec vq[D];
+    Ents<kEntTri> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, kEntTri>(eq[d], g, d, rs);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            {
+                const int4 h = hq[d];
+                const FwdVec &v = vq[d % D];
+                double *rp = row_ptr<S>(T, h.x, sc);
+                const double r = v.r - alpha * v.q;
+                const double dot = ring_dot<kEntTri>(eq[d % E], ring, lane_off);
+                const double y = r - (carry + dot);
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                rr += (h.x >= 0) ? r * r : 0.0;
+                ring_put(ring, h.y + lane_off, y);
+                rp[VR * S] = r;
+                rp[VY * S] = y;
+            }
+            fwd_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
+            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rr;
+}
+
+// ---- backward: z = U^-1 y, islanded rows zeroed on output, r'z ------------
+struct BwdVec {
+    double y, r, dinv;
+};
+
+template <int S>
+__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program &g, int s, int rs, const Tile &T,
+                                        int sc) {
+    constexpr int R = kWave / S;
+    const double *p = row_ptr<S>(T, h.x, sc);
+    v.y = p[VY * S];
+    v.r = p[VR * S];
+    v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
+}
+
+template <int S, int D>
+__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
+                                            int hi) {
+    constexpr int H = 2 * D, E = kEntAhead;
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rz = 0.0, carry = 0.0;
+    int4 hq[H];
+    BwdVec vq[D];
+    Ents<kEntTri> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g, d, rs, T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, kEntTri>(eq[d], g, d, rs);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            {
+                const int4 h = hq[d];
+                const BwdVec &v = vq[d % D];
+                const double dot = ring_dot<kEntTri>(eq[d % E], ring, lane_off);
+                const double z = (v.y - (carry + dot)) * v.dinv;
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                ring_put(ring, h.y + lane_off, z);
+                const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
+                row_ptr<S>(T, h.x, sc)[VY * S] = zm;
+                rz += (h.x >= 0) ? v.r * zm : 0.0;
+            }
+            bwd_vec<S>(vq[d % D], hq[(d + D) % H], g, s + D, rs, T, sc);
+            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rz;
+}
+
+// ---- product: on the look-ahead row delta += alpha p_old and p = z + beta
+// p_old (into the ring and memory); on the current row q = A_c p from the
+// ring with the outaged branch shielded, and p'q.  Natural row order.
+struct ProdVec {
+    double z, p, x;
+};
+
+template <int S>
+__device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
+    const double *p = row_ptr<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
+    v.z = p[VY * S];
+    v.p = p[VP * S];
+    v.x = p[VX * S];
+}
+
+template <int S, int D>
+__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                             double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
+                                             double bc) {
+    constexpr int H = 2 * D, E = kEntAhead;
+    const int lane_off = sc * 8;
+    const int wm = g.ring - 1;
+    const int zero = g.ring * S * 8;
+    const int trash = (g.ring + 1) * S * 8;
+    if (rs == 0) ring_put(ring, zero + lane_off, 0.0);
+    const int ic_off = ((ic >= 0) ? (ic & wm) * S * 8 : zero) + lane_off;
+    const int jc_off = ((jc >= 0) ? (jc & wm) * S * 8 : zero) + lane_off;
+    double pq = 0.0, carry = 0.0;
+    int4 hq[H];
+    ProdVec vq[D];
+    Ents<kEntProd> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], g, d, rs);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            {
+                const int4 h = hq[d];
+                const ProdVec &v = vq[d % D];
+                // look-ahead row: pending solution update and new direction
+                double *lp = row_ptr<S>(T, h.w, sc);
+                const double pn = done ? v.p : v.z + beta * v.p;
+                lp[VX * S] = v.x + alpha * v.p;
+                lp[VP * S] = pn;
+                ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
+                // current row
+                const double dot = ring_dot<kEntProd>(eq[d % E], ring, lane_off);
+                double qv = carry + dot;
+                carry = (h.z == -2) ? carry + dot : 0.0;
+                const double dpc = ring_at(ring, ic_off) - ring_at(ring, jc_off);
+                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
+                if (in_interval(h.z, lo, hi)) qv = 0.0;
+                row_ptr<S>(T, h.x, sc)[VQ * S] = qv;
+                pq += (h.x >= 0) ? ring_at(ring, h.y + lane_off) * qv : 0.0;
+            }
+            prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
+            load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return pq;
+}
+
+// delta += alpha p over every row (the update the product sweep would have
+// made next, applied once the tile stops)
+template <int S>
+__device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, double alpha) {
+    constexpr int R = kWave / S;
+    for (int i = rs; i < T.nr; i += R) {
+        double *rp = row_ptr<S>(T, i, sc);
+        rp[VX * S] += alpha * rp[VP * S];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile kernel: init, then PCG iterations until every column stops.
+template <int S, int D, int DP>
 __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     constexpr int R = kWave / S;
     extern __shared__ double ring[];
@@ -74,12 +339,9 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     const int scen = tile * S + sc;
     const bool valid = scen < p.n_out;
     const int nr = p.n_r;
-    const size_t vs = (size_t)nr * S;
-    double *X = p.ws + (size_t)tile * kVectors * vs;
-    double *Rv = X + vs;
-    double *Pv = Rv + vs;
-    double *Qv = Pv + vs;
-    double *Yv = Qv + vs;
+    Tile T;
+    T.base = p.ws + (size_t)tile * (nr + 1) * kVectors * S;  // n_r rows plus a scratch row
+    T.nr = nr;
 
     // ---- per-column outage data -------------------------------------------
     int c = valid ? p.outages[scen] : -1;
@@ -132,11 +394,15 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
             bb += b * b;
         }
         rr += r0 * r0;
-        const size_t o = (size_t)i * S + sc;
-        X[o] = 0.0;
-        Rv[o] = r0;
-        Pv[o] = 0.0;
-        Qv[o] = 0.0;
+        double *v = row_ptr<S>(T, i, sc);
+        v[VX * S] = 0.0;
+        v[VR * S] = r0;
+        v[VP * S] = 0.0;
+        v[VQ * S] = 0.0;
+    }
+    if (rs == 0) {
+        double *v = row_ptr<S>(T, nr, sc);
+        v[VX * S] = v[VR * S] = v[VP * S] = v[VQ * S] = v[VY * S] = 0.0;
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
@@ -160,27 +426,7 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     double alpha = 0.0, rho = 0.0;
     for (int k = 0;; ++k) {
         // ---- forward sweep: delta += alpha p, r -= alpha q, y = L^-1 r ----
-        double rrp = 0.0;
-        const bool upd = alpha != 0.0;
-        for (int s = 0; s < p.steps_f; ++s) {
-            const int row = (R == 1) ? s : p.sched_f[s * R + rs];
-            if (row >= 0) {
-                const size_t o = (size_t)row * S + sc;
-                double r = Rv[o];
-                if (upd) {
-                    X[o] += alpha * Pv[o];
-                    r -= alpha * Qv[o];
-                    Rv[o] = r;
-                }
-                rrp += r * r;
-                double y = r;
-                const int e1 = p.l_rowptr[row + 1];
-                for (int e = p.l_rowptr[row]; e < e1; ++e)
-                    y -= p.l_val[e] * ring[(p.l_col[e] & p.wmask_f) * S + sc];
-                ring[(row & p.wmask_f) * S + sc] = y;
-                Yv[o] = y;
-            }
-        }
+        double rrp = fwd_sweep<S, D>(p.fwd, ring, T, rs, sc, alpha);
         __syncthreads();
         rrp = col_sum<S>(rrp);
         if (k > 0 && !done) {
@@ -192,62 +438,26 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
                 done = true;
             }
         }
-        if (__all(done)) break;
-        if (k >= p.max_iter) {
-            if (!done) {
-                status = kMaxIter;
-                done = true;
-            }
+        if (k >= p.max_iter && !done) {
+            status = kMaxIter;
+            done = true;
+        }
+        if (__all(done)) {
+            // the last step length has not reached delta yet
+            final_update<S>(T, rs, sc, alpha);
             break;
         }
 
         // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
-        double rzp = 0.0;
-        for (int s = 0; s < p.steps_b; ++s) {
-            const int row = (R == 1) ? (nr - 1 - s) : p.sched_b[s * R + rs];
-            if (row >= 0) {
-                const size_t o = (size_t)row * S + sc;
-                double z = Yv[o];
-                const int e1 = p.u_rowptr[row + 1];
-                for (int e = p.u_rowptr[row]; e < e1; ++e)
-                    z -= p.u_val[e] * ring[(p.u_col[e] & p.wmask_b) * S + sc];
-                z *= p.u_invdiag[row];
-                ring[(row & p.wmask_b) * S + sc] = z;
-                const double zm = in_interval(p.pre_row[row], lo, hi) ? 0.0 : z;
-                Yv[o] = zm;
-                rzp += Rv[o] * zm;
-            }
-        }
+        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, lo, hi));
         __syncthreads();
-        const double rz = col_sum<S>(rzp);
-        double beta = (k == 0 || done) ? 0.0 : rz / rho;
+        const double beta = (k == 0 || done) ? 0.0 : rz / rho;
         rho = rz;
 
-        // ---- new direction p = z + beta p ----------------------------------
-        if (!done) {
-            for (int i = rs; i < nr; i += R) {
-                const size_t o = (size_t)i * S + sc;
-                Pv[o] = Yv[o] + beta * Pv[o];
-            }
-        }
+        // ---- p = z + beta p and q = A_c p (outaged branch shielded), p'q ---
+        const double sigma =
+            col_sum<S>(prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc));
         __syncthreads();
-
-        // ---- q = A_c p with the outaged branch shielded; sigma = p'q -------
-        const double dpc = ((ic >= 0) ? Pv[(size_t)ic * S + sc] : 0.0) - ((jc >= 0) ? Pv[(size_t)jc * S + sc] : 0.0);
-        double pqp = 0.0;
-        for (int i = rs; i < nr; i += R) {
-            double q = 0.0;
-            const int e1 = p.a_rowptr[i + 1];
-            for (int e = p.a_rowptr[i]; e < e1; ++e) q += p.a_val[e] * Pv[(size_t)p.a_col[e] * S + sc];
-            if (i == ic) q -= bc * dpc;
-            if (i == jc) q += bc * dpc;
-            if (in_interval(p.pre_row[i], lo, hi)) q = 0.0;
-            const size_t o = (size_t)i * S + sc;
-            Qv[o] = q;
-            pqp += Pv[o] * q;
-        }
-        __syncthreads();
-        const double sigma = col_sum<S>(pqp);
         if (!done) {
             if (!__builtin_isfinite(sigma) || !__builtin_isfinite(rho)) {
                 done = true;
@@ -289,7 +499,7 @@ __global__ void theta_out_kernel(OutParams p) {
     double th = 0.0;
     if (k > 0 && !in && !bad) {
         const int tile = s / p.S, sc = s % p.S;
-        th = p.theta_b[k] + p.ws[(size_t)tile * kVectors * p.n_r * p.S + (size_t)(k - 1) * p.S + sc];
+        th = p.theta_b[k] + p.ws[((size_t)tile * (p.n_r + 1) + (k - 1)) * kVectors * p.S + sc];
     }
     p.x_out[(size_t)s * p.n_bus + k] = th;
     if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
@@ -376,9 +586,10 @@ __global__ void base_residual_kernel(int n_r, const int32_t *__restrict__ rowptr
     rho[i] = h + l;
 }
 
+// theta_b += delta, delta read from tile 0 of a one-column (S = 1) workspace
 __global__ void base_accumulate_kernel(int n_r, double *theta_b, const double *delta) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_r) theta_b[i + 1] += delta[i];
+    if (i < n_r) theta_b[i + 1] += delta[(size_t)i * kVectors];
 }
 
 __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, double *out) {
@@ -455,21 +666,34 @@ __global__ void spmm_pq_reduce_kernel(int ncols, int chunks, const double *parti
 }  // namespace
 
 // ---------------------------------------------------------------------------
+constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
+constexpr int kPrefetchProd = 6;  // steps of prefetch in the product sweep
+
+template <int S>
+static hipError_t launch_pcg_s(const PcgParams &prm, int n_tiles, size_t lds, hipStream_t st) {
+    auto kern = pcg_tile_kernel<S, kPrefetch, kPrefetchProd>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, prm);
+    return hipGetLastError();
+}
+
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    const size_t lds = (size_t)ring_rows * S * sizeof(double);
-    dim3 grid(n_tiles), block(kWave);
+    // ring rows plus the zero row and the trash row of idle slots
+    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
     switch (S) {
-        case 1: hipLaunchKernelGGL(pcg_tile_kernel<1>, grid, block, lds, st, prm); break;
-        case 2: hipLaunchKernelGGL(pcg_tile_kernel<2>, grid, block, lds, st, prm); break;
-        case 4: hipLaunchKernelGGL(pcg_tile_kernel<4>, grid, block, lds, st, prm); break;
-        case 8: hipLaunchKernelGGL(pcg_tile_kernel<8>, grid, block, lds, st, prm); break;
-        case 16: hipLaunchKernelGGL(pcg_tile_kernel<16>, grid, block, lds, st, prm); break;
-        case 32: hipLaunchKernelGGL(pcg_tile_kernel<32>, grid, block, lds, st, prm); break;
-        case 64: hipLaunchKernelGGL(pcg_tile_kernel<64>, grid, block, lds, st, prm); break;
+        case 1: return launch_pcg_s<1>(prm, n_tiles, lds, st);
+        case 2: return launch_pcg_s<2>(prm, n_tiles, lds, st);
+        case 4: return launch_pcg_s<4>(prm, n_tiles, lds, st);
+        case 8: return launch_pcg_s<8>(prm, n_tiles, lds, st);
+        case 16: return launch_pcg_s<16>(prm, n_tiles, lds, st);
+        case 32: return launch_pcg_s<32>(prm, n_tiles, lds, st);
+        case 64: return launch_pcg_s<64>(prm, n_tiles, lds, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st) {
