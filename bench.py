@@ -239,7 +239,8 @@ def main():
     resid = out["resid"].cpu().numpy()
     S = info["block"]
     n_tiles = (m + S - 1) // S
-    tile_K = [int(iters[t * S:(t + 1) * S].max()) for t in range(n_tiles)]
+    it_tiles = iters[ctx.order(m)]  # iterations in tile order
+    tile_K = [int(it_tiles[t * S:(t + 1) * S].max()) for t in range(n_tiles)]
     algo_bytes = float(sum(tile_bytes(info, K, S) for K in tile_K))
     achieved = algo_bytes / (pcg_ms * 1e-3) / 1e9
     traffic = None

@@ -238,6 +238,16 @@ int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const doub
 int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, double *q, double *pq);
 
 /*
+ * Tile order of the last gpcg_solve_contingencies call: order[j] is the
+ * scenario solved in tile position j (tile j / S, column j % S).  Scenarios
+ * are grouped by expected work (non-islanding first, then islanding, each by
+ * the base-case flow of the outaged branch) so that the columns of a tile
+ * stop at about the same iteration.  order: host int32[n_out] (n_out of that
+ * call).  Synchronises the context's stream.
+ */
+int gpcg_get_order(gpcg_t h, int32_t n_out, int32_t *order);
+
+/*
  * Kernel timing.  With timing enabled, every solve records a HIP event on
  * the context's stream right before its first PCG kernel launch and one
  * right after its last, so the interval covers the PCG kernel(s) only (not

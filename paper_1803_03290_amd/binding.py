@@ -62,6 +62,7 @@ SIGNATURES = {
                                            _VP, _VP]),
     "gpcg_solve_plain": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
+    "gpcg_get_order": (C.c_int, [_VP, C.c_int32, _i32p]),
     "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
     "gpcg_get_timing": (C.c_int, [_VP, _f64p]),
 }
@@ -251,6 +252,12 @@ class Context:
                   _ptr(out["flows"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["island"]),
                   _ptr(out["resid"])))
         return out
+
+    def order(self, n_out) -> np.ndarray:
+        """gpcg_get_order: scenario per tile position of the last batched solve."""
+        o = np.zeros(n_out, np.int32)
+        _check(self._lib.gpcg_get_order(self._h, int(n_out), _ip(o)))
+        return o
 
     def set_timing(self, enable=True):
         """gpcg_set_timing: bracket every solve's PCG kernels with HIP events."""

@@ -505,6 +505,9 @@ struct gpcg_context {
     DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
+    DevBuf<uint32_t> keys, keys_sorted;
+    DevBuf<int32_t> iota, order, pos;
+    DevBuf<char> sort_temp;
     std::vector<std::vector<int>> deps_f, deps_b;  // for schedule building
     CsrH hA, hL, hU;                               // A, L, strict upper of U
     std::vector<double> h_invdiag;
@@ -515,6 +518,8 @@ struct gpcg_context {
     int base_iters = 0;
     double base_resid = 0.0;
     bool timing = false, timed = false;
+    int last_n_out = 0;
+    bool last_ordered = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     ~gpcg_context() {
@@ -621,6 +626,27 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
                                          h->rho_b.p, h->stream),
               "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
+    const int32_t *pos = nullptr;
+    if (S_ > 1 && n_out > S_) {
+        // group scenarios of similar expected work into the same tiles
+        if (h->keys.n < (size_t)n_out) {
+            h->keys.alloc(n_out);
+            h->keys_sorted.alloc(n_out);
+            h->iota.alloc(n_out);
+            h->order.alloc(n_out);
+            h->pos.alloc(n_out);
+        }
+        const size_t tb = gpcg::sort_temp_bytes(n_out);
+        if (h->sort_temp.n < tb) h->sort_temp.alloc(tb);
+        hip_check(gpcg::launch_order(n_out, outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
+                                     h->isl_hi.p, h->theta_b.p, h->keys.p, h->keys_sorted.p, h->iota.p, h->order.p,
+                                     h->pos.p, h->sort_temp.p, tb, h->stream),
+                  "scenario ordering");
+        p.order = h->order.p;
+        pos = h->pos.p;
+    }
+    h->last_n_out = n_out;
+    h->last_ordered = pos != nullptr;
     const int ring = D.ring_max();
     const int n_tiles = (n_out + S_ - 1) / S_;
     if (h->timing) hip_check(hipEventRecord(h->ev0, h->stream), "event");
@@ -657,6 +683,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.theta_b = h->theta_b.p;
     o.rhs = rhs;
     o.outages = outages;
+    o.pos = pos;
     o.ws = h->ws.p;
     o.status = status_out;
     o.gfac = h->gfac.p;
@@ -964,6 +991,21 @@ int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const doub
     return guarded([&] {
         run_solve(h, 1, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
                   resid_out);
+    });
+}
+
+int gpcg_get_order(gpcg_t h, int32_t n_out, int32_t *order) {
+    return guarded([&] {
+        if (!h || !order) fail(GPCG_E_ARG, "NULL argument");
+        if (n_out != h->last_n_out) fail(GPCG_E_ARG, "n_out differs from the last solve");
+        if (h->last_ordered) {
+            hip_check(hipMemcpyAsync(order, h->order.p, (size_t)n_out * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     h->stream),
+                      "copy");
+            hip_check(hipStreamSynchronize(h->stream), "sync");
+        } else {
+            for (int j = 0; j < n_out; ++j) order[j] = j;
+        }
     });
 }
 

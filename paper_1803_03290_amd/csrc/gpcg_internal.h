@@ -8,7 +8,7 @@
 namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
-constexpr int kVectors = 5;   // per tile and row: delta, r, p, q, y/z (interleaved per row)
+constexpr int kVectors = 5;   // per tile: delta, r, p, q, y/z, each (n_r + 1) x S
 constexpr int kLdsBudget = 80 * 1024;  // bytes of LDS ring per wavefront (two waves fit one CU)
 
 enum Status : int32_t {
@@ -27,7 +27,7 @@ enum Status : int32_t {
 // carries their partial sums.
 constexpr int kPadSteps = 32;  // idle steps appended to every program (>= the deepest prefetch)
 constexpr int kEntTri = 4;
-constexpr int kEntProd = 6;
+constexpr int kEntProd = 8;
 
 // A sweep program: the steps one wavefront walks, R row slots per step, each
 // slot with a fixed number K of packed matrix entries (padding entries carry
@@ -67,13 +67,14 @@ struct PcgParams {
     const double *theta_b;  // n_bus, slack 0
     const double *rho_b;    // n_r: rhs - A theta_b
     const double *rhs;      // n_bus
-    // scenarios
+    // scenarios: tile position j solves scenario order[j] (NULL: j itself)
     const int32_t *outages;
+    const int32_t *order;
     int n_out;
     int tile0;  // first tile of this launch (plain mode launches one tile at a time)
     double tol2;
     int max_iter;
-    double *ws;  // tiles x (n_r + 1) rows x kVectors x S
+    double *ws;  // tiles x kVectors x (n_r + 1) rows x S
     int32_t *iters_out, *status_out;
     double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
 };
@@ -88,6 +89,7 @@ struct OutParams {
     const int32_t *isl_lo, *isl_hi;
     const double *theta_b, *rhs;
     const int32_t *outages;
+    const int32_t *pos;  // tile position of each scenario (NULL: the scenario index)
     const double *ws;
     const int32_t *status;
     const double *gfac;
@@ -118,5 +120,16 @@ hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta,
 int spmm_chunks(int n_r);
 hipError_t launch_spmm_partial(const SpmmParams &prm, int S, double *partial, hipStream_t st);
 hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st);
+
+// Order scenarios by expected PCG work so that a tile's columns stop at
+// about the same iteration: non-islanding outages first, then islanding
+// ones, each by the base-case flow of the outaged branch.  Writes order[]
+// (scenario per tile position) and pos[] (its inverse).  temp / temp_bytes:
+// scratch from sort_temp_bytes().
+size_t sort_temp_bytes(int n);
+hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
+                        const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi, const double *theta_b,
+                        uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order, int32_t *pos, void *temp,
+                        size_t temp_bytes, hipStream_t st);
 
 }  // namespace gpcg

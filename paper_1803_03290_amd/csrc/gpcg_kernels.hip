@@ -23,6 +23,7 @@
 #include "gpcg_internal.h"
 
 #include <climits>
+#include <hipcub/hipcub.hpp>
 
 namespace gpcg {
 namespace {
@@ -72,9 +73,10 @@ __device__ __forceinline__ void dd_fma(double &hi, double &lo, double a, double 
 // (row n_r) and the ring's trash row, and padding entries are real zero
 // entries in memory.
 //
-// A tile stores its five vectors interleaved per row: element (row i,
-// vector v, column sc) at (i * 5 + v) * S + sc, so one address per step
-// reaches every vector of a row with immediate offsets.
+// A tile stores its five vectors one after the other, each row-major with
+// S columns: a wave's access to one vector row is S contiguous doubles, and
+// every sweep reads only the vectors it needs.  Vector bases are wave-uniform
+// (scalar registers); a step computes one 32-bit offset for all of them.
 enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
 constexpr int kEntAhead = 2;
 
@@ -109,23 +111,50 @@ __device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, i
     for (int j = 0; j < K; ++j) E.e[j] = base[j * R];
 }
 
-// sum_j v_j * ring[col_j] for the lane's column (lane_off = sc * 8)
+// A step's ring values and entry values, gathered before the step's refill
+// loads are issued so that the LDS reads are in flight meanwhile.
 template <int K>
-__device__ __forceinline__ double ring_dot(const Ents<K> &E, const double *ring, int lane_off) {
+struct Gath {
+    double r[K], v[K];
+};
+
+template <int K>
+__device__ __forceinline__ void gather(Gath<K> &G, const Ents<K> &E, const double *ring, int lane_off) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        G.r[j] = ring_at(ring, E.e[j].z + lane_off);
+        G.v[j] = __hiloint2double(E.e[j].y, E.e[j].x);
+    }
+}
+
+// sum_j v_j * ring[col_j]
+template <int K>
+__device__ __forceinline__ double gdot(const Gath<K> &G) {
     double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc += __hiloint2double(E.e[j].y, E.e[j].x) * ring_at(ring, E.e[j].z + lane_off);
+    for (int j = 0; j < K; ++j) acc += G.v[j] * G.r[j];
     return acc;
 }
 
+// A tile's five vectors, each (n_r + 1) rows x S columns (row n_r is scratch).
 struct Tile {
-    double *base;  // row 0, vector 0, column 0 of the tile
+    double *v[kVectors];
     int nr;
 };
 
+// byte offset of (row, column sc) inside any vector of a tile; idle slots
+// (row -1) go to the scratch row
 template <int S>
-__device__ __forceinline__ double *row_ptr(const Tile &T, int row, int sc) {
-    return T.base + ((size_t)(row >= 0 ? row : T.nr) * kVectors) * S + sc;
+__device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
+    return ((unsigned)(row >= 0 ? row : T.nr) * S + sc) * 8u;
+}
+
+__device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
+    return *(const double *)((const char *)T.v[v] + off);
+}
+
+__device__ __forceinline__ void vput(const Tile &T, int v, unsigned off, double x) {
+    *(double *)((char *)T.v[v] + off) = x;
 }
 
 // Programs end with kPadSteps idle steps, so reading past the last real step
@@ -144,9 +173,9 @@ struct FwdVec {
 
 template <int S>
 __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
-    const double *p = row_ptr<S>(T, h.x, sc);
-    v.r = p[VR * S];
-    v.q = p[VQ * S];
+    const unsigned o = row_off<S>(T, h.x, sc);
+    v.r = vget(T, VR, o);
+    v.q = vget(T, VQ, o);
 }
 
 template <int S, int D>
@@ -169,22 +198,25 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
+            const int4 h = hq[d];
+            const FwdVec v = vq[d % D];
+            Gath<kEntTri> G;
+            gather(G, eq[d % E], ring, lane_off);
+            // refills: independent of this step, issued while its LDS reads fly
+            fwd_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
+            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
             {
-                const int4 h = hq[d];
-                const FwdVec &v = vq[d % D];
-                double *rp = row_ptr<S>(T, h.x, sc);
+                const unsigned o = row_off<S>(T, h.x, sc);
                 const double r = v.r - alpha * v.q;
-                const double dot = ring_dot<kEntTri>(eq[d % E], ring, lane_off);
+                const double dot = gdot(G);
                 const double y = r - (carry + dot);
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 rr += (h.x >= 0) ? r * r : 0.0;
                 ring_put(ring, h.y + lane_off, y);
-                rp[VR * S] = r;
-                rp[VY * S] = y;
+                vput(T, VR, o, r);
+                vput(T, VY, o, y);
             }
-            fwd_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
-            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -200,9 +232,9 @@ template <int S>
 __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program &g, int s, int rs, const Tile &T,
                                         int sc) {
     constexpr int R = kWave / S;
-    const double *p = row_ptr<S>(T, h.x, sc);
-    v.y = p[VY * S];
-    v.r = p[VR * S];
+    const unsigned o = row_off<S>(T, h.x, sc);
+    v.y = vget(T, VY, o);
+    v.r = vget(T, VR, o);
     v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
 }
 
@@ -226,20 +258,22 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
+            const int4 h = hq[d];
+            const BwdVec v = vq[d % D];
+            Gath<kEntTri> G;
+            gather(G, eq[d % E], ring, lane_off);
+            bwd_vec<S>(vq[d % D], hq[(d + D) % H], g, s + D, rs, T, sc);
+            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
             {
-                const int4 h = hq[d];
-                const BwdVec &v = vq[d % D];
-                const double dot = ring_dot<kEntTri>(eq[d % E], ring, lane_off);
+                const double dot = gdot(G);
                 const double z = (v.y - (carry + dot)) * v.dinv;
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 ring_put(ring, h.y + lane_off, z);
                 const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
-                row_ptr<S>(T, h.x, sc)[VY * S] = zm;
+                vput(T, VY, row_off<S>(T, h.x, sc), zm);
                 rz += (h.x >= 0) ? v.r * zm : 0.0;
             }
-            bwd_vec<S>(vq[d % D], hq[(d + D) % H], g, s + D, rs, T, sc);
-            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -255,10 +289,10 @@ struct ProdVec {
 
 template <int S>
 __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
-    const double *p = row_ptr<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
-    v.z = p[VY * S];
-    v.p = p[VP * S];
-    v.x = p[VX * S];
+    const unsigned o = row_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
+    v.z = vget(T, VY, o);
+    v.p = vget(T, VP, o);
+    v.x = vget(T, VX, o);
 }
 
 template <int S, int D>
@@ -287,28 +321,32 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
-            {
-                const int4 h = hq[d];
-                const ProdVec &v = vq[d % D];
-                // look-ahead row: pending solution update and new direction
-                double *lp = row_ptr<S>(T, h.w, sc);
-                const double pn = done ? v.p : v.z + beta * v.p;
-                lp[VX * S] = v.x + alpha * v.p;
-                lp[VP * S] = pn;
-                ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
-                // current row
-                const double dot = ring_dot<kEntProd>(eq[d % E], ring, lane_off);
-                double qv = carry + dot;
-                carry = (h.z == -2) ? carry + dot : 0.0;
-                const double dpc = ring_at(ring, ic_off) - ring_at(ring, jc_off);
-                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
-                if (in_interval(h.z, lo, hi)) qv = 0.0;
-                row_ptr<S>(T, h.x, sc)[VQ * S] = qv;
-                pq += (h.x >= 0) ? ring_at(ring, h.y + lane_off) * qv : 0.0;
-            }
+            const int4 h = hq[d];
+            const ProdVec v = vq[d % D];
+            // look-ahead row: pending solution update and new direction (its
+            // ring write must precede this step's reads)
+            const unsigned lo_ = row_off<S>(T, h.w, sc);
+            const double pn = done ? v.p : v.z + beta * v.p;
+            ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
+            Gath<kEntProd> G;
+            gather(G, eq[d % E], ring, lane_off);
+            const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
+            const double pown = ring_at(ring, h.y + lane_off);
             prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
             load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
             hq[d] = load_head<S>(g, s + H, rs);
+            {
+                vput(T, VX, lo_, v.x + alpha * v.p);
+                vput(T, VP, lo_, pn);
+                const double dot = gdot(G);
+                double qv = carry + dot;
+                carry = (h.z == -2) ? carry + dot : 0.0;
+                const double dpc = pf - pt;
+                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
+                if (in_interval(h.z, lo, hi)) qv = 0.0;
+                vput(T, VQ, row_off<S>(T, h.x, sc), qv);
+                pq += (h.x >= 0) ? pown * qv : 0.0;
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -321,8 +359,8 @@ template <int S>
 __device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, double alpha) {
     constexpr int R = kWave / S;
     for (int i = rs; i < T.nr; i += R) {
-        double *rp = row_ptr<S>(T, i, sc);
-        rp[VX * S] += alpha * rp[VP * S];
+        const unsigned o = row_off<S>(T, i, sc);
+        vput(T, VX, o, vget(T, VX, o) + alpha * vget(T, VP, o));
     }
 }
 
@@ -336,11 +374,12 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     const int sc = lane % S;
     const int rs = lane / S;
     const int tile = blockIdx.x + p.tile0;
-    const int scen = tile * S + sc;
-    const bool valid = scen < p.n_out;
+    const int posn = tile * S + sc;  // tile position of this column
+    const bool valid = posn < p.n_out;
+    const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
     const int nr = p.n_r;
     Tile T;
-    T.base = p.ws + (size_t)tile * (nr + 1) * kVectors * S;  // n_r rows plus a scratch row
+    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * (nr + 1) * S;
     T.nr = nr;
 
     // ---- per-column outage data -------------------------------------------
@@ -394,15 +433,15 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
             bb += b * b;
         }
         rr += r0 * r0;
-        double *v = row_ptr<S>(T, i, sc);
-        v[VX * S] = 0.0;
-        v[VR * S] = r0;
-        v[VP * S] = 0.0;
-        v[VQ * S] = 0.0;
+        const unsigned o = row_off<S>(T, i, sc);
+        vput(T, VX, o, 0.0);
+        vput(T, VR, o, r0);
+        vput(T, VP, o, 0.0);
+        vput(T, VQ, o, 0.0);
     }
     if (rs == 0) {
-        double *v = row_ptr<S>(T, nr, sc);
-        v[VX * S] = v[VR * S] = v[VP * S] = v[VQ * S] = v[VY * S] = 0.0;
+        const unsigned o = row_off<S>(T, nr, sc);
+        for (int v = 0; v < kVectors; ++v) vput(T, v, o, 0.0);
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
@@ -498,8 +537,9 @@ __global__ void theta_out_kernel(OutParams p) {
     const bool in = (k > 0) && in_interval(p.pre_bus[k], lo, hi);
     double th = 0.0;
     if (k > 0 && !in && !bad) {
-        const int tile = s / p.S, sc = s % p.S;
-        th = p.theta_b[k] + p.ws[((size_t)tile * (p.n_r + 1) + (k - 1)) * kVectors * p.S + sc];
+        const int j = p.pos ? p.pos[s] : s;
+        const int tile = j / p.S, sc = j % p.S;
+        th = p.theta_b[k] + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
     }
     p.x_out[(size_t)s * p.n_bus + k] = th;
     if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
@@ -589,7 +629,7 @@ __global__ void base_residual_kernel(int n_r, const int32_t *__restrict__ rowptr
 // theta_b += delta, delta read from tile 0 of a one-column (S = 1) workspace
 __global__ void base_accumulate_kernel(int n_r, double *theta_b, const double *delta) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_r) theta_b[i + 1] += delta[(size_t)i * kVectors];
+    if (i < n_r) theta_b[i + 1] += delta[i];
 }
 
 __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, double *out) {
@@ -663,7 +703,50 @@ __global__ void spmm_pq_reduce_kernel(int ncols, int chunks, const double *parti
     pq[col] = a;
 }
 
+// sort key of a scenario: islanding flag, then the base flow on the branch
+__global__ void order_keys_kernel(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
+                                  const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi,
+                                  const double *theta_b, uint32_t *keys, int32_t *iota) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int c = outages[j];
+    uint32_t key = 0;
+    if (c < -1 || c >= m) {
+        key = 0xffffffffu;
+    } else if (c >= 0) {
+        const float f = (float)fabs(br_b[c] * (theta_b[br_from[c]] - theta_b[br_to[c]]));
+        key = (__float_as_uint(f) >> 1) | (isl_hi[c] > isl_lo[c] ? 0x80000000u : 0u);
+    }
+    keys[j] = key;
+    iota[j] = j;
+}
+
+__global__ void order_inverse_kernel(int n, const int32_t *order, int32_t *pos) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) pos[order[j]] = j;
+}
+
 }  // namespace
+
+size_t sort_temp_bytes(int n) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (const int32_t *)nullptr, (int32_t *)nullptr, n);
+    return bytes;
+}
+
+hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
+                        const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi, const double *theta_b,
+                        uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order, int32_t *pos, void *temp,
+                        size_t temp_bytes, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, outages, m, br_from, br_to, br_b,
+                       isl_lo, isl_hi, theta_b, keys, iota);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, iota, order, n, 0, 32, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(order_inverse_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, order, pos);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
