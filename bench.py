@@ -148,6 +148,47 @@ def cpu_baseline(grid, seconds: float = 12.0):
             "cpu_model": model}
 
 
+# ------------------------------------------------------ stand-alone SpMM
+def spmm_measure(gp, torch, workload: str, S: int = 64, reps: int = 20):
+    """The outage-corrected product q = A_c p over every outage column of a
+    grid in one launch (p ~ N(0, 1), seed 0, columns padded to a multiple
+    of S), timed with HIP events; bytes are the product's algorithmic bytes
+    12 nnz + 4 (n_r + 1) + 16 n_r s + 16 s for s columns."""
+    import gridgen
+    import numpy as np
+
+    grid = gridgen.make_grid(workload)
+    ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=S)
+    info = ctx.info()
+    nr = info["n_r"]
+    ncols = ((grid.m + S - 1) // S) * S
+    dev = torch.device("cuda", 0)
+    outs = torch.tensor(np.arange(ncols) % grid.m, dtype=torch.int32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    p = torch.randn((ncols // S, nr, S), dtype=torch.float64, device=dev, generator=gen)
+    q = torch.empty_like(p)
+    pq = torch.empty(ncols, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        ctx.spmm(outs, p, q, pq)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.spmm(outs, p, q, pq)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    nbytes = 12.0 * info["nnz_a"] + 4.0 * (nr + 1) + 16.0 * nr * ncols + 16.0 * ncols
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"{grid.name}: q = A_c p over {ncols} outage columns ({grid.m} outages)",
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "median_ms": ms, "algorithmic_bytes": nbytes, "block": S}
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -164,6 +205,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--spmm-workload", default="grid10k", help="grid of the stand-alone product measurement")
+    ap.add_argument("--no-spmm", action="store_true")
+    ap.add_argument("--spmm-block", type=int, default=4)
+    ap.add_argument("--spmm-only", action="store_true", help="only the stand-alone product measurement")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -187,10 +232,17 @@ def main():
         n = 1 << 27  # 1 GiB of float64
         a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0.record()
         for _ in range(5):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}))
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 6,
+                          "ms_per_copy": ms, "GBps": 2 * n * 8 / (ms * 1e-3) / 1e9}))
         return
 
     import paper_1803_03290_amd as gp
@@ -198,6 +250,9 @@ def main():
     gp.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.spmm_only:
+        print(json.dumps(spmm_measure(gp, torch, args.spmm_workload, args.spmm_block)), flush=True)
+        return
     t0 = time.perf_counter()
     block = args.block or auto_block(grid.m)
     ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=block)
@@ -266,6 +321,8 @@ def main():
                  "ms": p_ms, "max_abs_diff_vs_batched_rad": same,
                  "note": "seeded sample, one scenario per launch, lanes spread over rows (S=1)"}
 
+    spmm = None if args.no_spmm else spmm_measure(gp, torch, args.spmm_workload, args.spmm_block)
+
     value = m / (ms_step * 1e-3)
     st_counts = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
     res = {
@@ -295,6 +352,7 @@ def main():
             "kernel": f"pcg_tile_kernel<{S}>", "algorithmic_bytes_per_launch": algo_bytes,
             "avg_launch_ms": pcg_ms, "kernel_digest": kernel_digest(),
         },
+        "spmm": spmm,
         "cpu_baseline": cpu,
         "verify": {
             "status_counts": st_counts,

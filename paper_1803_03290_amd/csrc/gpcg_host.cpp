@@ -1057,11 +1057,15 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
         s.pq = pq;
         double *partial = nullptr;
         if (pq) {
-            const size_t need = (size_t)gpcg::spmm_chunks(h->n_r) * ncols;
+            const size_t need = (size_t)ncols;
             if (h->partial.n < need) h->partial.alloc(need);
             partial = h->partial.p;
         }
-        hip_check(gpcg::launch_spmm_partial(s, h->S, partial, h->stream), "spmm launch");
+        const int ch = gpcg::kSpmmChunk;
+        int max_nnz = 0;
+        for (int r0 = 0; r0 < h->n_r; r0 += ch)
+            max_nnz = std::max(max_nnz, h->hA.rowptr[std::min(h->n_r, r0 + ch)] - h->hA.rowptr[r0]);
+        hip_check(gpcg::launch_spmm_partial(s, h->S, h->bandwidth, max_nnz, partial, h->stream), "spmm launch");
     });
 }
 

@@ -115,10 +115,13 @@ hipError_t launch_outputs(const OutParams &prm, hipStream_t st);
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
                                 const double *theta_b, const double *rhs, double *rho, hipStream_t st);
 hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta, hipStream_t st);
-// q = A_c p over ncols / S tiles; partial: f64[spmm_chunks(n_r) * ncols]
+// q = A_c p over ncols / S tiles (bw: bandwidth of A); partial: f64[ncols]
 // scratch for the p'q column sums (NULL when prm.pq is NULL).
-int spmm_chunks(int n_r);
-hipError_t launch_spmm_partial(const SpmmParams &prm, int S, double *partial, hipStream_t st);
+// max_nnz: the most entries of A in any chunk of kSpmmChunk rows; partial
+// holds ncols doubles.
+constexpr int kSpmmChunk = 128;   // rows per chunk of the stand-alone product
+constexpr int kSpmmMaxEnt = 1024;  // entries of A per chunk it can stage
+hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int max_nnz, double *partial, hipStream_t st);
 hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st);
 
 // Order scenarios by expected PCG work so that a tile's columns stop at

@@ -22,6 +22,7 @@
 // overwritten.
 #include "gpcg_internal.h"
 
+#include <algorithm>
 #include <climits>
 #include <hipcub/hipcub.hpp>
 
@@ -646,25 +647,35 @@ __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, doub
 }
 
 // ---------------------------------------------------------------------------
-// Stand-alone outage-corrected product q = A_c p over many tiles.  A wave
-// takes a chunk of rows of one tile; the blocks of one tile are placed on
-// the same XCD (work-groups are dealt to the 8 XCDs round-robin) so that the
-// neighbour rows one wave reads were fetched into that XCD's L2 by another.
-constexpr int kSpmmRows = 64;  // rows per wave
-constexpr int kXcd = 8;
+// Stand-alone outage-corrected product q = A_c p over many tiles.  One
+// work-group streams one tile from the first row to the last through an LDS
+// ring of p rows: at each chunk it loads the rows the next chunk will need
+// (bw rows beyond it) and the chunk's slice of A with contiguous loads, then
+// forms q for the chunk's (row, column) pairs from LDS.  Every row of p is
+// read from memory once per tile, every entry of A once per chunk.
+constexpr int kSpmmThreads = 256;
 
 template <int S>
-__global__ void __launch_bounds__(256) spmm_kernel(SpmmParams p, int chunks, int n_tiles, double *partial) {
-    constexpr int R = kWave / S;
-    const int xcd = blockIdx.x % kXcd;
-    const int idx = blockIdx.x / kXcd;
-    const int wave = threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int chunk = (idx % ((chunks + 3) / 4)) * 4 + wave;
-    const int tile = (idx / ((chunks + 3) / 4)) * kXcd + xcd;
-    if (tile >= n_tiles || chunk >= chunks) return;
-    const int sc = lane % S, rs = lane / S;
+__global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmParams p, int ring, int bw, double *partial) {
+    extern __shared__ double lds[];
+    constexpr int RS = kSpmmThreads / S;  // row slots
+    constexpr int CH = kSpmmChunk;
+    constexpr int NP = (CH * S + kSpmmThreads - 1) / kSpmmThreads;  // p doubles per thread per chunk
+    constexpr int NE = kSpmmMaxEnt / kSpmmThreads;                   // entries of A per thread per chunk
+    const int tile = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int sc = tid % S, rs = tid / S;
     const int col = tile * S + sc;
+    const int nr = p.n_r;
+    const int wm = ring - 1;
+    const size_t vs = (size_t)nr * S;
+    const double *P = p.p + (size_t)tile * vs;
+    double *Q = p.q + (size_t)tile * vs;
+    double *pr = lds;                                               // ring x S
+    double *lval = lds + (size_t)(ring > RS ? ring : RS) * S;  // chunk slice of A
+    int *lcol = (int *)(lval + kSpmmMaxEnt);
+    int *lrp = lcol + kSpmmMaxEnt;
+
     const int c = p.outages[col];
     int ic = -1, jc = -1, lo = 0, hi = 0;
     double bc = 0.0;
@@ -675,24 +686,78 @@ __global__ void __launch_bounds__(256) spmm_kernel(SpmmParams p, int chunks, int
         lo = p.isl_lo[c];
         hi = p.isl_hi[c];
     }
-    const size_t vs = (size_t)p.n_r * S;
-    const double *P = p.p + (size_t)tile * vs;
-    double *Q = p.q + (size_t)tile * vs;
     const double dpc = ((ic >= 0) ? P[(size_t)ic * S + sc] : 0.0) - ((jc >= 0) ? P[(size_t)jc * S + sc] : 0.0);
+
+    // registers holding the next chunk's new p rows and slice of A
+    double rp[NP];
+    double rv[NE];
+    int rcol[NE], rrp = 0;
+    int ra = 0, rb = 0, re0 = 0, rne = 0;
+    auto fetch = [&](int c0) {  // loads for chunk c0: p rows [c0 + bw, c0 + CH + bw), A rows [c0, c0 + CH)
+        const int c1 = min(nr, c0 + CH);
+        ra = min(nr, max(0, c0 + bw));
+        rb = min(nr, c1 + bw);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int t = tid + k * kSpmmThreads;
+            rp[k] = (t < (rb - ra) * S) ? P[(size_t)ra * S + t] : 0.0;
+        }
+        re0 = p.a_rowptr[c0];
+        rne = p.a_rowptr[c1] - re0;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int t = tid + k * kSpmmThreads;
+            rv[k] = (t < rne) ? p.a_val[re0 + t] : 0.0;
+            rcol[k] = (t < rne) ? p.a_col[re0 + t] : 0;
+        }
+        rrp = (tid <= c1 - c0) ? p.a_rowptr[c0 + tid] - re0 : 0;
+    };
+    auto commit = [&](int c0) {  // registers -> LDS
+        const int c1 = min(nr, c0 + CH);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int t = tid + k * kSpmmThreads;
+            if (t < (rb - ra) * S) pr[((ra + t / S) & wm) * S + t % S] = rp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int t = tid + k * kSpmmThreads;
+            if (t < rne) {
+                lval[t] = rv[k];
+                lcol[t] = rcol[k] & wm;
+            }
+        }
+        if (tid <= c1 - c0) lrp[tid] = rrp;
+    };
+    // rows [0, bw) of p
+    for (int t = tid; t < min(bw, nr) * S; t += kSpmmThreads) pr[((t / S) & wm) * S + t % S] = P[t];
+    fetch(0);
     double pq = 0.0;
-    const int r0 = chunk * kSpmmRows, r1 = min(p.n_r, r0 + kSpmmRows);
-    for (int i = r0 + rs; i < r1; i += R) {
-        double q = 0.0;
-        const int e1 = p.a_rowptr[i + 1];
-        for (int e = p.a_rowptr[i]; e < e1; ++e) q += p.a_val[e] * P[(size_t)p.a_col[e] * S + sc];
-        if (i == ic) q -= bc * dpc;
-        if (i == jc) q += bc * dpc;
-        if (in_interval(p.pre_row[i], lo, hi)) q = 0.0;
-        Q[(size_t)i * S + sc] = q;
-        pq += P[(size_t)i * S + sc] * q;
+    for (int c0 = 0; c0 < nr; c0 += CH) {
+        const int c1 = min(nr, c0 + CH);
+        commit(c0);
+        __syncthreads();
+        if (c1 < nr) fetch(c1);  // in flight while this chunk is formed
+        for (int i = c0 + rs; i < c1; i += RS) {
+            double q = 0.0;
+            const int b0 = lrp[i - c0], b1 = lrp[i - c0 + 1];
+            for (int e = b0; e < b1; ++e) q += lval[e] * pr[lcol[e] * S + sc];
+            if (i == ic) q -= bc * dpc;
+            if (i == jc) q += bc * dpc;
+            if (in_interval(p.pre_row[i], lo, hi)) q = 0.0;
+            Q[(size_t)i * S + sc] = q;
+            pq += pr[(i & wm) * S + sc] * q;
+        }
+        __syncthreads();
     }
-    pq = col_sum<S>(pq);
-    if (partial && rs == 0) partial[(size_t)chunk * p.ncols + col] = pq;
+    // column sums of p'q over the row slots, in a fixed order
+    pr[tid] = pq;
+    __syncthreads();
+    if (tid < S) {
+        double a = 0.0;
+        for (int k = 0; k < RS; ++k) a += pr[k * S + sc];
+        if (partial) partial[col] = a;
+    }
 }
 
 __global__ void spmm_pq_reduce_kernel(int ncols, int chunks, const double *partial, double *pq) {
@@ -808,28 +873,43 @@ hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st) {
     return hipGetLastError();
 }
 
-int spmm_chunks(int n_r) { return (n_r + kSpmmRows - 1) / kSpmmRows; }
+// ring rows: the chunk plus bw rows on either side, rounded up to a power of two
+int spmm_ring_rows(int bw) {
+    int W = 1;
+    while (W < kSpmmChunk + 2 * bw + 1) W <<= 1;
+    return W;
+}
 
-hipError_t launch_spmm_partial(const SpmmParams &prm, int S, double *partial, hipStream_t st) {
+template <int S>
+static hipError_t launch_spmm_s(const SpmmParams &prm, int bw, int max_nnz, double *partial, hipStream_t st) {
     const int n_tiles = prm.ncols / S;
-    const int chunks = (prm.n_r + kSpmmRows - 1) / kSpmmRows;
-    const int groups = (chunks + 3) / 4;
-    const int tile_rounds = (n_tiles + kXcd - 1) / kXcd;
-    dim3 grid((unsigned)(tile_rounds * groups * kXcd)), block(256);
-    switch (S) {
-        case 1: hipLaunchKernelGGL(spmm_kernel<1>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 2: hipLaunchKernelGGL(spmm_kernel<2>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 4: hipLaunchKernelGGL(spmm_kernel<4>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 8: hipLaunchKernelGGL(spmm_kernel<8>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 16: hipLaunchKernelGGL(spmm_kernel<16>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 32: hipLaunchKernelGGL(spmm_kernel<32>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        case 64: hipLaunchKernelGGL(spmm_kernel<64>, grid, block, 0, st, prm, chunks, n_tiles, partial); break;
-        default: return hipErrorInvalidValue;
+    const int ring = spmm_ring_rows(bw);
+    const size_t lds = (size_t)std::max(ring, kSpmmThreads / S) * S * sizeof(double) +
+                       (size_t)kSpmmMaxEnt * (sizeof(double) + sizeof(int)) + (size_t)(kSpmmChunk + 1) * sizeof(int);
+    if (max_nnz > kSpmmMaxEnt) return hipErrorInvalidValue;
+    auto kern = spmm_kernel<S>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_tiles), dim3(kSpmmThreads), lds, st, prm, ring, bw, partial);
     if (partial && prm.pq)
-        hipLaunchKernelGGL(spmm_pq_reduce_kernel, dim3((prm.ncols + 255) / 256), dim3(256), 0, st, prm.ncols, chunks,
+        hipLaunchKernelGGL(spmm_pq_reduce_kernel, dim3((prm.ncols + 255) / 256), dim3(256), 0, st, prm.ncols, 1,
                            partial, prm.pq);
     return hipGetLastError();
+}
+
+hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int max_nnz, double *partial, hipStream_t st) {
+    switch (S) {
+        case 1: return launch_spmm_s<1>(prm, bw, max_nnz, partial, st);
+        case 2: return launch_spmm_s<2>(prm, bw, max_nnz, partial, st);
+        case 4: return launch_spmm_s<4>(prm, bw, max_nnz, partial, st);
+        case 8: return launch_spmm_s<8>(prm, bw, max_nnz, partial, st);
+        case 16: return launch_spmm_s<16>(prm, bw, max_nnz, partial, st);
+        case 32: return launch_spmm_s<32>(prm, bw, max_nnz, partial, st);
+        case 64: return launch_spmm_s<64>(prm, bw, max_nnz, partial, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace gpcg
