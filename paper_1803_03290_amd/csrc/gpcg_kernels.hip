@@ -79,7 +79,8 @@ __device__ __forceinline__ void dd_fma(double &hi, double &lo, double a, double 
 // every sweep reads only the vectors it needs.  Vector bases are wave-uniform
 // (scalar registers); a step computes one 32-bit offset for all of them.
 enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
-constexpr int kEntAhead = 2;
+constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
+constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
 
 // The step index as a vector register the compiler cannot see through.
 // Without it a wave-uniform index makes the loaded row id uniform too, and
@@ -182,7 +183,7 @@ __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T,
 template <int S, int D>
 __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                             double alpha) {
-    constexpr int H = 2 * D, E = kEntAhead;
+    constexpr int H = 2 * D, E = kEntAheadTri;
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rr = 0.0, carry = 0.0;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program 
 template <int S, int D>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
                                             int hi) {
-    constexpr int H = 2 * D, E = kEntAhead;
+    constexpr int H = 2 * D, E = kEntAheadTri;
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rz = 0.0, carry = 0.0;
@@ -300,7 +301,7 @@ template <int S, int D>
 __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                              double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
                                              double bc) {
-    constexpr int H = 2 * D, E = kEntAhead;
+    constexpr int H = 2 * D, E = kEntAheadProd;
     const int lane_off = sc * 8;
     const int wm = g.ring - 1;
     const int zero = g.ring * S * 8;
