@@ -168,6 +168,43 @@ __device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
     return g.rec[ss * R + rs];
 }
 
+// ---- triangular sweeps -----------------------------------------------------
+// Consecutive steps of a triangular solve may depend on each other through
+// the ring, so a step is split in two.  Part A is the chain: finish the ring
+// dot product, form the row's value, write it to the ring and issue the next
+// step's ring reads.  Part B holds the rest of the step (stores, the next
+// step's right-hand side and carry, refills)
+// and is issued while those reads are in flight.  The right-hand side enters
+// as (rhs - carry) - dot, one subtraction on the chain.
+
+// ring byte addresses of a step's entries for this lane
+template <int K>
+__device__ __forceinline__ void ring_addr(int (&a)[K], const Ents<K> &E, int lane_off) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] = E.e[j].z + lane_off;
+}
+
+template <int K>
+__device__ __forceinline__ void ring_read(double (&r)[K], const int (&a)[K], const double *ring) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) r[j] = ring_at(ring, a[j]);
+}
+
+// sum_j v_j * ring[col_j] as a pairwise tree (short dependency chain)
+template <int K>
+__device__ __forceinline__ double tree_dot(const double (&r)[K], const Ents<K> &E) {
+    double acc[K / 2];
+#pragma unroll
+    for (int j = 0; j < K / 2; ++j)
+        acc[j] = __builtin_fma(__hiloint2double(E.e[2 * j + 1].y, E.e[2 * j + 1].x), r[2 * j + 1],
+                               __hiloint2double(E.e[2 * j].y, E.e[2 * j].x) * r[2 * j]);
+#pragma unroll
+    for (int w = 1; w < K / 2; w <<= 1)
+#pragma unroll
+        for (int j = 0; j + w < K / 2; j += 2 * w) acc[j] += acc[j + w];
+    return acc[0];
+}
+
 // ---- forward: r -= alpha q, ||r||^2, y = L^-1 r ---------------------------
 struct FwdVec {
     double r, q;
@@ -183,42 +220,53 @@ __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T,
 template <int S, int D>
 __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                             double alpha) {
-    constexpr int H = 2 * D, E = kEntAheadTri;
+    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
+    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rr = 0.0, carry = 0.0;
     int4 hq[H];
     FwdVec vq[D];
-    Ents<kEntTri> eq[E];
+    Ents<K> eq[E];
 #pragma unroll
     for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
 #pragma unroll
     for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, kEntTri>(eq[d], g, d, rs);
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double r = vq[0].r - alpha * vq[0].q;  // step 0's residual row
+    double rc = r;                         // ... minus its carry
+    fwd_vec<S>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
             const int4 h = hq[d];
-            const FwdVec v = vq[d % D];
-            Gath<kEntTri> G;
-            gather(G, eq[d % E], ring, lane_off);
-            // refills: independent of this step, issued while its LDS reads fly
-            fwd_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
-            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
+            // A
+            const double dot = tree_dot(G, eq[d % E]);
+            const double y = rc - dot;
+            ring_put(ring, h.y + lane_off, y);
+            ring_addr(ga, eq[(d + 1) % E], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
             {
                 const unsigned o = row_off<S>(T, h.x, sc);
-                const double r = v.r - alpha * v.q;
-                const double dot = gdot(G);
-                const double y = r - (carry + dot);
-                carry = (h.w == 1) ? carry + dot : 0.0;
-                rr += (h.x >= 0) ? r * r : 0.0;
-                ring_put(ring, h.y + lane_off, y);
                 vput(T, VR, o, r);
                 vput(T, VY, o, y);
+                rr += (h.x >= 0) ? r * r : 0.0;
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                const FwdVec v = vq[(d + 1) % D];
+                r = v.r - alpha * v.q;
+                rc = r - carry;
             }
+            load_ents<S, K>(eq[d % E], g, s + E, rs);
+            fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            hq[d] = load_head<S>(g, s + H, rs);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -243,39 +291,52 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program 
 template <int S, int D>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
                                             int hi) {
-    constexpr int H = 2 * D, E = kEntAheadTri;
+    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
+    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rz = 0.0, carry = 0.0;
     int4 hq[H];
     BwdVec vq[D];
-    Ents<kEntTri> eq[E];
+    Ents<K> eq[E];
 #pragma unroll
     for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
 #pragma unroll
     for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g, d, rs, T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, kEntTri>(eq[d], g, d, rs);
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double yc = vq[0].y, dv = vq[0].dinv, r = vq[0].r;  // step 0's row
+    bwd_vec<S>(vq[0], hq[D], g, D, rs, T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
             const int4 h = hq[d];
-            const BwdVec v = vq[d % D];
-            Gath<kEntTri> G;
-            gather(G, eq[d % E], ring, lane_off);
-            bwd_vec<S>(vq[d % D], hq[(d + D) % H], g, s + D, rs, T, sc);
-            load_ents<S, kEntTri>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
+            // A
+            const double dot = tree_dot(G, eq[d % E]);
+            const double z = (yc - dot) * dv;
+            ring_put(ring, h.y + lane_off, z);
+            ring_addr(ga, eq[(d + 1) % E], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
             {
-                const double dot = gdot(G);
-                const double z = (v.y - (carry + dot)) * v.dinv;
-                carry = (h.w == 1) ? carry + dot : 0.0;
-                ring_put(ring, h.y + lane_off, z);
                 const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
                 vput(T, VY, row_off<S>(T, h.x, sc), zm);
-                rz += (h.x >= 0) ? v.r * zm : 0.0;
+                rz += (h.x >= 0) ? r * zm : 0.0;
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                const BwdVec v = vq[(d + 1) % D];
+                yc = v.y - carry;
+                dv = v.dinv;
+                r = v.r;
             }
+            load_ents<S, K>(eq[d % E], g, s + E, rs);
+            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g, s + 1 + D, rs, T, sc);
+            hq[d] = load_head<S>(g, s + H, rs);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
