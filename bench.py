@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "N-1 scenario solves/sec to 1e-10 residual, batched vs plain PCG; HBM GB/s %"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "pcg_tile_grid2k_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_tile.hip")
 
 # Vector passes (8 bytes per row per scenario column each) of the tile kernel
 # as written: init writes delta, r, p, q; a forward sweep reads r, q and
@@ -71,7 +71,10 @@ def auto_block(n_out: int) -> int:
 
 
 def read_counters():
-    """(fetch_kib, write_kib, copy_factor, digest) from the committed summary."""
+    """(fetch_kib, write_kib, fetch_factor, write_factor, digest, (workload,
+    block)) from the
+    committed summary; each factor is what a plain copy of known size needs
+    to turn that counter into bytes."""
     if not os.path.exists(COUNTERS):
         return None
     vals = {}
@@ -81,7 +84,8 @@ def read_counters():
             vals[k.strip()] = v.strip()
     try:
         return (float(vals["fetch_kib_per_dispatch"]), float(vals["write_kib_per_dispatch"]),
-                float(vals["copy_factor"]), vals["kernel_digest"])
+                float(vals["fetch_copy_factor"]), float(vals["write_copy_factor"]), vals["kernel_digest"],
+                (vals["workload"], int(vals["block"])))
     except KeyError:
         return None
 
@@ -300,8 +304,8 @@ def main():
     achieved = algo_bytes / (pcg_ms * 1e-3) / 1e9
     traffic = None
     cnt = read_counters()
-    if cnt and cnt[3] == kernel_digest():
-        traffic = (cnt[0] + cnt[1]) * 1024.0 * cnt[2]
+    if cnt and cnt[4] == kernel_digest() and cnt[5] == (args.workload, S):
+        traffic = cnt[0] * 1024.0 * cnt[2] + cnt[1] * 1024.0 * cnt[3]
 
     plain = None
     if not args.no_plain:

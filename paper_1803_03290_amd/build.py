@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpcg.so")
-SOURCES = [os.path.join(CSRC, "gpcg_host.cpp"), os.path.join(CSRC, "gpcg_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "gpcg_host.cpp"), os.path.join(CSRC, "gpcg_tile.hip"),
+           os.path.join(CSRC, "gpcg_kernels.hip")]
 ARCH = os.environ.get("GPCG_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (the kernels are

@@ -505,6 +505,9 @@ struct gpcg_context {
     DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
+    int spmm_ch = 0, spmm_max_nnz = 0;  // chunk layout of A the stand-alone product reads
+    DevBuf<double> c_val;
+    DevBuf<int32_t> c_col, c_rp, c_pre;
     DevBuf<uint32_t> keys, keys_sorted;
     DevBuf<int32_t> iota, order, pos;
     DevBuf<char> sort_temp;
@@ -1038,34 +1041,73 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
         if (!h || !outages || !p || !q) fail(GPCG_E_ARG, "NULL argument");
         if (ncols <= 0 || ncols % h->S) fail(GPCG_E_ARG, "ncols must be a positive multiple of the block");
         hip_check(hipSetDevice(h->device), "hipSetDevice");
+        // rows per chunk: the most that the per-thread staging takes and that
+        // keep the work-group's LDS in budget; segments of up to 8 chunks
+        const int S = h->S, RS = 256 / S, nr = h->n_r, bw = h->bandwidth;
+        const auto &rp = h->hA.rowptr;
+        auto chunk_nnz = [&](int ch) {
+            int mx = 0;
+            for (int r0 = 0; r0 < nr; r0 += ch) mx = std::max(mx, rp[std::min(nr, r0 + ch)] - rp[r0]);
+            return mx;
+        };
+        int ch = 0, max_nnz = 0;
+        for (int c = (8192 / S) / RS * RS; c >= RS; c -= RS) {
+            const int mx = chunk_nnz(c);
+            if (!gpcg::spmm_chunk_fits(S, c, mx)) continue;
+            ch = c;
+            max_nnz = mx;
+            if (gpcg::spmm_lds_bytes(S, bw, c, mx) <= gpcg::kSpmmLdsBudget) break;
+        }
+        if (ch == 0 || gpcg::spmm_lds_bytes(S, bw, ch, max_nnz) > 160 * 1024)
+            fail(GPCG_E_UNSUPPORTED, "the matrix bandwidth is too large for the product's LDS window at this block");
+        const int n_chunks = (nr + ch - 1) / ch;
+        if (h->spmm_ch != ch) {  // lay A out per chunk (once per chunk height)
+            std::vector<double> val((size_t)n_chunks * max_nnz, 0.0);
+            std::vector<int32_t> col((size_t)n_chunks * max_nnz, 0), rpc((size_t)n_chunks * (ch + 1)),
+                pre((size_t)n_chunks * ch, -1);
+            for (int k = 0; k < n_chunks; ++k) {
+                const int c0 = k * ch, c1 = std::min(nr, c0 + ch), base = std::max(0, c0 - bw), e0 = rp[c0];
+                for (int e = e0; e < rp[c1]; ++e) {
+                    val[(size_t)k * max_nnz + e - e0] = h->hA.val[e];
+                    col[(size_t)k * max_nnz + e - e0] = h->hA.col[e] - base;
+                }
+                for (int t = 0; t <= ch; ++t) rpc[(size_t)k * (ch + 1) + t] = rp[std::min(c1, c0 + t)] - e0;
+                for (int t = 0; t < ch && c0 + t < nr; ++t) pre[(size_t)k * ch + t] = h->h_prerow[c0 + t];
+            }
+            h->spmm_ch = 0;
+            h->c_val.upload(val.data(), val.size(), h->stream);
+            h->c_col.upload(col.data(), col.size(), h->stream);
+            h->c_rp.upload(rpc.data(), rpc.size(), h->stream);
+            h->c_pre.upload(pre.data(), pre.size(), h->stream);
+            hip_check(hipStreamSynchronize(h->stream), "product layout upload");
+            h->spmm_ch = ch;
+            h->spmm_max_nnz = max_nnz;
+        }
         gpcg::SpmmParams s{};
-        s.n_r = h->n_r;
+        s.n_r = nr;
         s.m = h->m;
         s.ncols = ncols;
-        s.a_rowptr = h->a_rowptr.p;
-        s.a_col = h->a_col.p;
-        s.a_val = h->a_val.p;
+        s.c_val = h->c_val.p;
+        s.c_col = h->c_col.p;
+        s.c_rp = h->c_rp.p;
+        s.c_pre = h->c_pre.p;
         s.br_from = h->br_from.p;
         s.br_to = h->br_to.p;
         s.br_b = h->br_b.p;
-        s.pre_row = h->pre_row.p;
         s.isl_lo = h->isl_lo.p;
         s.isl_hi = h->isl_hi.p;
         s.outages = outages;
         s.p = p;
         s.q = q;
         s.pq = pq;
+        const int nseg = std::min(n_chunks, 8);
         double *partial = nullptr;
         if (pq) {
-            const size_t need = (size_t)ncols;
+            const size_t need = (size_t)((n_chunks + nseg - 1) / nseg) * ncols;
             if (h->partial.n < need) h->partial.alloc(need);
             partial = h->partial.p;
         }
-        const int ch = gpcg::kSpmmChunk;
-        int max_nnz = 0;
-        for (int r0 = 0; r0 < h->n_r; r0 += ch)
-            max_nnz = std::max(max_nnz, h->hA.rowptr[std::min(h->n_r, r0 + ch)] - h->hA.rowptr[r0]);
-        hip_check(gpcg::launch_spmm_partial(s, h->S, h->bandwidth, max_nnz, partial, h->stream), "spmm launch");
+        hip_check(gpcg::launch_spmm_partial(s, S, bw, ch, nseg, max_nnz, partial, h->stream), "spmm launch");
     });
 }
 

@@ -1,5 +1,6 @@
 // Internal declarations shared by the host side (gpcg_host.cpp) and the
-// device kernels (gpcg_kernels.hip) of the batched contingency PCG library.
+// device kernels (gpcg_tile.hip, gpcg_kernels.hip) of the batched contingency
+// PCG library.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,31 +98,42 @@ struct OutParams {
     uint8_t *island_out;
 };
 
+// The stand-alone product reads A through a per-chunk copy laid out on the
+// host once per chunk height ch: chunk k holds max_nnz entries at
+// k * max_nnz (values; columns as row offsets from the chunk's lowest read
+// row max(0, k ch - bw); padding has value 0 and offset 0), ch + 1 row
+// pointers relative to the chunk's first entry at k (ch + 1), and the ch
+// rows' pre-order numbers at k ch.  No staging load then depends on another.
 struct SpmmParams {
     int n_r, m, ncols;
-    const int32_t *a_rowptr, *a_col;
-    const double *a_val;
+    const double *c_val;
+    const int32_t *c_col, *c_rp, *c_pre;
     const int32_t *br_from, *br_to;
     const double *br_b;
-    const int32_t *pre_row, *isl_lo, *isl_hi;
+    const int32_t *isl_lo, *isl_hi;
     const int32_t *outages;
     const double *p;
     double *q, *pq;
 };
 
-// Launchers (gpcg_kernels.hip).  They return hipSuccess or the launch error.
+// Launchers (launch_pcg in gpcg_tile.hip, the rest in gpcg_kernels.hip).  They
+// return hipSuccess or the launch error.
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st);
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st);
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
                                 const double *theta_b, const double *rhs, double *rho, hipStream_t st);
 hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta, hipStream_t st);
-// q = A_c p over ncols / S tiles (bw: bandwidth of A); partial: f64[ncols]
-// scratch for the p'q column sums (NULL when prm.pq is NULL).
-// max_nnz: the most entries of A in any chunk of kSpmmChunk rows; partial
-// holds ncols doubles.
-constexpr int kSpmmChunk = 128;   // rows per chunk of the stand-alone product
-constexpr int kSpmmMaxEnt = 1024;  // entries of A per chunk it can stage
-hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int max_nnz, double *partial, hipStream_t st);
+// q = A_c p over ncols / S tiles of n_r x S (bw: bandwidth of A).  Rows are
+// cut into chunks of ch (a multiple of 256 / S that spmm_chunk_fits accepts)
+// and chunks into segments of nseg, one work-group per (tile, segment);
+// max_nnz: the most entries of A in one chunk.  partial:
+// f64[n_segments * ncols] scratch for the p'q column sums (NULL when prm.pq
+// is NULL).
+constexpr size_t kSpmmLdsBudget = 40 * 1024;  // LDS per work-group the host aims for (four fit one CU)
+size_t spmm_lds_bytes(int S, int bw, int ch, int max_nnz);
+bool spmm_chunk_fits(int S, int ch, int max_nnz);
+hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int ch, int nseg, int max_nnz, double *partial,
+                               hipStream_t st);
 hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st);
 
 // Order scenarios by expected PCG work so that a tile's columns stop at

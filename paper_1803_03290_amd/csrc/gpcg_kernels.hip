@@ -1,44 +1,15 @@
-// Device kernels of the batched "N-1" contingency PCG (gfx950, wave64, FP64).
-//
-// Layout.  Scenarios are grouped S to a tile; one wavefront owns one tile and
-// carries it through the whole preconditioned CG of Section III.A.  Its 64
-// lanes are R x S with R = 64 / S: lane = rs * S + sc treats scenario column
-// sc and row slot rs.  Per tile the workspace holds five vectors: delta (the
-// change of state from the base case), r, p, q = A_c p, and y / z (the
-// forward-solve result, overwritten by the backward-solve result).  They are
-// interleaved per row: element (row i, vector v, column sc) at
-// (i * 5 + v) * S + sc, so a wave touching a row reads S contiguous doubles
-// per vector, all five vectors of a row lie together, and every matrix entry
-// it reads is shared by the S columns.
-//
-// The outage of branch c = (f, t) is applied as a rank-1 correction of the
-// shared base matrix: A_c = A - b_c u u^T with u = e_f - e_t (Section IV.B:
-// four entries change), so no per-scenario matrix exists.  Islanded buses
-// (a DFS pre-order interval of the bridge's far side) are held at zero.
-//
-// The triangular solves run through a schedule of steps of R independent
-// rows each; values the next rows depend on are kept in an LDS ring of
-// 2^k rows x S columns, sized on the host so that no live value is
-// overwritten.
-#include "gpcg_internal.h"
+// Device kernels of the batched "N-1" contingency PCG other than the tile
+// kernel: outputs and true residuals, the base-case helpers, the stand-alone
+// outage-corrected product and the scenario ordering (gfx950, FP64).
+#include "gpcg_device.h"
 
 #include <algorithm>
 #include <climits>
 #include <hipcub/hipcub.hpp>
+#include <type_traits>
 
 namespace gpcg {
 namespace {
-
-template <int S>
-__device__ __forceinline__ double col_sum(double v) {
-    // butterfly over the R lanes of one column; every lane gets the same
-    // bits because each addition is commutative
-#pragma unroll
-    for (int off = S; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-__device__ __forceinline__ bool in_interval(int v, int lo, int hi) { return v >= lo && v < hi; }
 
 // ---------------------------------------------------------------------------
 // double-double helpers (Dekker 1971; Ogita, Rump, Oishi 2005): error-free
@@ -59,528 +30,6 @@ __device__ __forceinline__ void dd_fma(double &hi, double &lo, double a, double 
     two_sum(hi, p, s, e);
     hi = s;
     lo += e + pe;
-}
-
-// ---------------------------------------------------------------------------
-// Sweeps.  Each sweep walks its program step by step through a three-stage
-// register pipeline: a step's row record is loaded H = 2D steps ahead, its
-// vector rows D steps ahead and its matrix entries E = 2 steps ahead (they
-// are shared by every wave and sit in L1/L2).  A step first consumes its
-// pipeline slots and then refills them with later steps, so no register is
-// copied, no load waits on another load still in flight, and a step only
-// waits on the LDS ring that carries the dependencies between rows.
-// Vector-memory counters complete in order, so the loop has no branches
-// around loads and stores: idle slots read and write the tile's scratch row
-// (row n_r) and the ring's trash row, and padding entries are real zero
-// entries in memory.
-//
-// A tile stores its five vectors one after the other, each row-major with
-// S columns: a wave's access to one vector row is S contiguous doubles, and
-// every sweep reads only the vectors it needs.  Vector bases are wave-uniform
-// (scalar registers); a step computes one 32-bit offset for all of them.
-enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
-constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
-constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
-
-// The step index as a vector register the compiler cannot see through.
-// Without it a wave-uniform index makes the loaded row id uniform too, and
-// the compiler copies it to a scalar register right after the load, which
-// waits for every load in flight.
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
-__device__ __forceinline__ double ring_at(const double *ring, int byte_off) {
-    return *(const double *)((const char *)ring + byte_off);
-}
-
-__device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
-    *(double *)((char *)ring + byte_off) = v;
-}
-
-template <int K>
-struct Ents {
-    int3 e[K];
-};
-
-template <int S, int K>
-__device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, int rs) {
-    constexpr int R = kWave / S;
-    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
-    const int3 *base = g.ent + ((size_t)ss * K) * R + rs;
-#pragma unroll
-    for (int j = 0; j < K; ++j) E.e[j] = base[j * R];
-}
-
-// A step's ring values and entry values, gathered before the step's refill
-// loads are issued so that the LDS reads are in flight meanwhile.
-template <int K>
-struct Gath {
-    double r[K], v[K];
-};
-
-template <int K>
-__device__ __forceinline__ void gather(Gath<K> &G, const Ents<K> &E, const double *ring, int lane_off) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        G.r[j] = ring_at(ring, E.e[j].z + lane_off);
-        G.v[j] = __hiloint2double(E.e[j].y, E.e[j].x);
-    }
-}
-
-// sum_j v_j * ring[col_j]
-template <int K>
-__device__ __forceinline__ double gdot(const Gath<K> &G) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) acc += G.v[j] * G.r[j];
-    return acc;
-}
-
-// A tile's five vectors, each (n_r + 1) rows x S columns (row n_r is scratch).
-struct Tile {
-    double *v[kVectors];
-    int nr;
-};
-
-// byte offset of (row, column sc) inside any vector of a tile; idle slots
-// (row -1) go to the scratch row
-template <int S>
-__device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
-    return ((unsigned)(row >= 0 ? row : T.nr) * S + sc) * 8u;
-}
-
-__device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
-    return *(const double *)((const char *)T.v[v] + off);
-}
-
-__device__ __forceinline__ void vput(const Tile &T, int v, unsigned off, double x) {
-    *(double *)((char *)T.v[v] + off) = x;
-}
-
-// Programs end with kPadSteps idle steps, so reading past the last real step
-// only needs a clamp (no branch that would wait for the load).
-template <int S>
-__device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
-    constexpr int R = kWave / S;
-    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
-    return g.rec[ss * R + rs];
-}
-
-// ---- triangular sweeps -----------------------------------------------------
-// Consecutive steps of a triangular solve may depend on each other through
-// the ring, so a step is split in two.  Part A is the chain: finish the ring
-// dot product, form the row's value, write it to the ring and issue the next
-// step's ring reads.  Part B holds the rest of the step (stores, the next
-// step's right-hand side and carry, refills)
-// and is issued while those reads are in flight.  The right-hand side enters
-// as (rhs - carry) - dot, one subtraction on the chain.
-
-// ring byte addresses of a step's entries for this lane
-template <int K>
-__device__ __forceinline__ void ring_addr(int (&a)[K], const Ents<K> &E, int lane_off) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) a[j] = E.e[j].z + lane_off;
-}
-
-template <int K>
-__device__ __forceinline__ void ring_read(double (&r)[K], const int (&a)[K], const double *ring) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) r[j] = ring_at(ring, a[j]);
-}
-
-// sum_j v_j * ring[col_j] as a pairwise tree (short dependency chain)
-template <int K>
-__device__ __forceinline__ double tree_dot(const double (&r)[K], const Ents<K> &E) {
-    double acc[K / 2];
-#pragma unroll
-    for (int j = 0; j < K / 2; ++j)
-        acc[j] = __builtin_fma(__hiloint2double(E.e[2 * j + 1].y, E.e[2 * j + 1].x), r[2 * j + 1],
-                               __hiloint2double(E.e[2 * j].y, E.e[2 * j].x) * r[2 * j]);
-#pragma unroll
-    for (int w = 1; w < K / 2; w <<= 1)
-#pragma unroll
-        for (int j = 0; j + w < K / 2; j += 2 * w) acc[j] += acc[j + w];
-    return acc[0];
-}
-
-// ---- forward: r -= alpha q, ||r||^2, y = L^-1 r ---------------------------
-struct FwdVec {
-    double r, q;
-};
-
-template <int S>
-__device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
-    const unsigned o = row_off<S>(T, h.x, sc);
-    v.r = vget(T, VR, o);
-    v.q = vget(T, VQ, o);
-}
-
-template <int S, int D>
-__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
-                                            double alpha) {
-    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
-    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
-    const int lane_off = sc * 8;
-    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
-    double rr = 0.0, carry = 0.0;
-    int4 hq[H];
-    FwdVec vq[D];
-    Ents<K> eq[E];
-#pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
-#pragma unroll
-    for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
-#pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
-    int ga[K];
-    double G[K];
-    ring_addr(ga, eq[0], lane_off);
-    ring_read(G, ga, ring);
-    double r = vq[0].r - alpha * vq[0].q;  // step 0's residual row
-    double rc = r;                         // ... minus its carry
-    fwd_vec<S>(vq[0], hq[D], T, sc);
-    for (int s0 = 0; s0 < g.steps; s0 += H) {
-#pragma unroll
-        for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
-            const int4 h = hq[d];
-            // A
-            const double dot = tree_dot(G, eq[d % E]);
-            const double y = rc - dot;
-            ring_put(ring, h.y + lane_off, y);
-            ring_addr(ga, eq[(d + 1) % E], lane_off);
-            ring_read(G, ga, ring);
-            __builtin_amdgcn_sched_barrier(0);
-            // B
-            {
-                const unsigned o = row_off<S>(T, h.x, sc);
-                vput(T, VR, o, r);
-                vput(T, VY, o, y);
-                rr += (h.x >= 0) ? r * r : 0.0;
-                carry = (h.w == 1) ? carry + dot : 0.0;
-                const FwdVec v = vq[(d + 1) % D];
-                r = v.r - alpha * v.q;
-                rc = r - carry;
-            }
-            load_ents<S, K>(eq[d % E], g, s + E, rs);
-            fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = load_head<S>(g, s + H, rs);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    return rr;
-}
-
-// ---- backward: z = U^-1 y, islanded rows zeroed on output, r'z ------------
-struct BwdVec {
-    double y, r, dinv;
-};
-
-template <int S>
-__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program &g, int s, int rs, const Tile &T,
-                                        int sc) {
-    constexpr int R = kWave / S;
-    const unsigned o = row_off<S>(T, h.x, sc);
-    v.y = vget(T, VY, o);
-    v.r = vget(T, VR, o);
-    v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
-}
-
-template <int S, int D>
-__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
-                                            int hi) {
-    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
-    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
-    const int lane_off = sc * 8;
-    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
-    double rz = 0.0, carry = 0.0;
-    int4 hq[H];
-    BwdVec vq[D];
-    Ents<K> eq[E];
-#pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
-#pragma unroll
-    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g, d, rs, T, sc);
-#pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
-    int ga[K];
-    double G[K];
-    ring_addr(ga, eq[0], lane_off);
-    ring_read(G, ga, ring);
-    double yc = vq[0].y, dv = vq[0].dinv, r = vq[0].r;  // step 0's row
-    bwd_vec<S>(vq[0], hq[D], g, D, rs, T, sc);
-    for (int s0 = 0; s0 < g.steps; s0 += H) {
-#pragma unroll
-        for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
-            const int4 h = hq[d];
-            // A
-            const double dot = tree_dot(G, eq[d % E]);
-            const double z = (yc - dot) * dv;
-            ring_put(ring, h.y + lane_off, z);
-            ring_addr(ga, eq[(d + 1) % E], lane_off);
-            ring_read(G, ga, ring);
-            __builtin_amdgcn_sched_barrier(0);
-            // B
-            {
-                const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
-                vput(T, VY, row_off<S>(T, h.x, sc), zm);
-                rz += (h.x >= 0) ? r * zm : 0.0;
-                carry = (h.w == 1) ? carry + dot : 0.0;
-                const BwdVec v = vq[(d + 1) % D];
-                yc = v.y - carry;
-                dv = v.dinv;
-                r = v.r;
-            }
-            load_ents<S, K>(eq[d % E], g, s + E, rs);
-            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g, s + 1 + D, rs, T, sc);
-            hq[d] = load_head<S>(g, s + H, rs);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    return rz;
-}
-
-// ---- product: on the look-ahead row delta += alpha p_old and p = z + beta
-// p_old (into the ring and memory); on the current row q = A_c p from the
-// ring with the outaged branch shielded, and p'q.  Natural row order.
-struct ProdVec {
-    double z, p, x;
-};
-
-template <int S>
-__device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
-    const unsigned o = row_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
-    v.z = vget(T, VY, o);
-    v.p = vget(T, VP, o);
-    v.x = vget(T, VX, o);
-}
-
-template <int S, int D>
-__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
-                                             double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
-                                             double bc) {
-    constexpr int H = 2 * D, E = kEntAheadProd;
-    const int lane_off = sc * 8;
-    const int wm = g.ring - 1;
-    const int zero = g.ring * S * 8;
-    const int trash = (g.ring + 1) * S * 8;
-    if (rs == 0) ring_put(ring, zero + lane_off, 0.0);
-    const int ic_off = ((ic >= 0) ? (ic & wm) * S * 8 : zero) + lane_off;
-    const int jc_off = ((jc >= 0) ? (jc & wm) * S * 8 : zero) + lane_off;
-    double pq = 0.0, carry = 0.0;
-    int4 hq[H];
-    ProdVec vq[D];
-    Ents<kEntProd> eq[E];
-#pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
-#pragma unroll
-    for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
-#pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], g, d, rs);
-    for (int s0 = 0; s0 < g.steps; s0 += H) {
-#pragma unroll
-        for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
-            const int4 h = hq[d];
-            const ProdVec v = vq[d % D];
-            // look-ahead row: pending solution update and new direction (its
-            // ring write must precede this step's reads)
-            const unsigned lo_ = row_off<S>(T, h.w, sc);
-            const double pn = done ? v.p : v.z + beta * v.p;
-            ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
-            Gath<kEntProd> G;
-            gather(G, eq[d % E], ring, lane_off);
-            const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
-            const double pown = ring_at(ring, h.y + lane_off);
-            prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
-            load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
-            {
-                vput(T, VX, lo_, v.x + alpha * v.p);
-                vput(T, VP, lo_, pn);
-                const double dot = gdot(G);
-                double qv = carry + dot;
-                carry = (h.z == -2) ? carry + dot : 0.0;
-                const double dpc = pf - pt;
-                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
-                if (in_interval(h.z, lo, hi)) qv = 0.0;
-                vput(T, VQ, row_off<S>(T, h.x, sc), qv);
-                pq += (h.x >= 0) ? pown * qv : 0.0;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    return pq;
-}
-
-// delta += alpha p over every row (the update the product sweep would have
-// made next, applied once the tile stops)
-template <int S>
-__device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, double alpha) {
-    constexpr int R = kWave / S;
-    for (int i = rs; i < T.nr; i += R) {
-        const unsigned o = row_off<S>(T, i, sc);
-        vput(T, VX, o, vget(T, VX, o) + alpha * vget(T, VP, o));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// The tile kernel: init, then PCG iterations until every column stops.
-template <int S, int D, int DP>
-__global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
-    constexpr int R = kWave / S;
-    extern __shared__ double ring[];
-    const int lane = threadIdx.x;
-    const int sc = lane % S;
-    const int rs = lane / S;
-    const int tile = blockIdx.x + p.tile0;
-    const int posn = tile * S + sc;  // tile position of this column
-    const bool valid = posn < p.n_out;
-    const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
-    const int nr = p.n_r;
-    Tile T;
-    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * (nr + 1) * S;
-    T.nr = nr;
-
-    // ---- per-column outage data -------------------------------------------
-    int c = valid ? p.outages[scen] : -1;
-    const bool bad = valid && (c < -1 || c >= p.m);
-    if (bad) c = -1;
-    int ic = -1, jc = -1, lo = 0, hi = 0;
-    double bc = 0.0;
-    if (c >= 0) {
-        ic = p.br_from[c] - 1;
-        jc = p.br_to[c] - 1;
-        bc = p.br_b[c];
-        lo = p.isl_lo[c];
-        hi = p.isl_hi[c];
-    }
-    if (bad) {
-        lo = 0;
-        hi = INT_MAX;
-    }
-    const bool island = hi > lo;
-
-    // ---- re-dispatch (Section IV.C): islanded power over main generators --
-    double dP = 0.0, Sg = 0.0;
-    for (int i = rs; i < nr; i += R) {
-        const double Pk = p.rhs[i + 1];
-        if (in_interval(p.pre_row[i], lo, hi))
-            dP += Pk;
-        else if (Pk > 0.0)
-            Sg += Pk;
-    }
-    dP = col_sum<S>(dP);
-    Sg = col_sum<S>(Sg);
-    const bool nogen = island && !(Sg > 0.0);
-    const double gfac = (p.kind == 0 && island && !bad && !nogen) ? dP / Sg : 0.0;
-
-    // ---- correction-form start from the base state --------------------------
-    // r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
-    const double thf = (ic >= 0) ? p.theta_b[ic + 1] : 0.0;
-    const double tht = (jc >= 0) ? p.theta_b[jc + 1] : 0.0;
-    const double corr = bc * (thf - tht);
-    double rr = 0.0, bb = 0.0;
-    for (int i = rs; i < nr; i += R) {
-        double r0 = 0.0;
-        if (!in_interval(p.pre_row[i], lo, hi)) {
-            const double Pk = p.rhs[i + 1];
-            const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
-            r0 = dPk + p.rho_b[i];
-            if (i == ic) r0 += corr;
-            if (i == jc) r0 -= corr;
-            const double b = Pk + dPk;
-            bb += b * b;
-        }
-        rr += r0 * r0;
-        const unsigned o = row_off<S>(T, i, sc);
-        vput(T, VX, o, 0.0);
-        vput(T, VR, o, r0);
-        vput(T, VP, o, 0.0);
-        vput(T, VQ, o, 0.0);
-    }
-    if (rs == 0) {
-        const unsigned o = row_off<S>(T, nr, sc);
-        for (int v = 0; v < kVectors; ++v) vput(T, v, o, 0.0);
-    }
-    rr = col_sum<S>(rr);
-    bb = col_sum<S>(bb);
-
-    int status = kConverged;
-    int iters = 0;
-    bool done;
-    if (!valid) {
-        done = true;
-    } else if (bad) {
-        done = true;
-        status = kBadOutage;
-    } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(bb)) {
-        done = true;
-        status = kNonfinite;
-    } else {
-        done = rr <= p.tol2 * bb;
-    }
-    __syncthreads();
-
-    double alpha = 0.0, rho = 0.0;
-    for (int k = 0;; ++k) {
-        // ---- forward sweep: delta += alpha p, r -= alpha q, y = L^-1 r ----
-        double rrp = fwd_sweep<S, D>(p.fwd, ring, T, rs, sc, alpha);
-        __syncthreads();
-        rrp = col_sum<S>(rrp);
-        if (k > 0 && !done) {
-            iters = k;
-            if (!__builtin_isfinite(rrp)) {
-                done = true;
-                status = kNonfinite;
-            } else if (rrp <= p.tol2 * bb) {
-                done = true;
-            }
-        }
-        if (k >= p.max_iter && !done) {
-            status = kMaxIter;
-            done = true;
-        }
-        if (__all(done)) {
-            // the last step length has not reached delta yet
-            final_update<S>(T, rs, sc, alpha);
-            break;
-        }
-
-        // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
-        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, lo, hi));
-        __syncthreads();
-        const double beta = (k == 0 || done) ? 0.0 : rz / rho;
-        rho = rz;
-
-        // ---- p = z + beta p and q = A_c p (outaged branch shielded), p'q ---
-        const double sigma =
-            col_sum<S>(prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc));
-        __syncthreads();
-        if (!done) {
-            if (!__builtin_isfinite(sigma) || !__builtin_isfinite(rho)) {
-                done = true;
-                status = kNonfinite;
-            } else if (!(sigma > 0.0)) {
-                done = true;
-                status = kBreakdown;
-            } else {
-                alpha = rho / sigma;
-            }
-        }
-        if (done) alpha = 0.0;
-    }
-
-    if (valid && rs == 0) {
-        int st = status;
-        if (st == kConverged && island) st = (p.kind == 0 && nogen) ? kIslandedNoGen : kConvergedIslanded;
-        p.iters_out[scen] = iters;
-        p.status_out[scen] = st;
-        p.gfac_out[scen] = gfac;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -709,34 +158,131 @@ __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, doub
 }
 
 // ---------------------------------------------------------------------------
-// Stand-alone outage-corrected product q = A_c p over many tiles.  One
-// work-group streams one tile from the first row to the last through an LDS
-// ring of p rows: at each chunk it loads the rows the next chunk will need
-// (bw rows beyond it) and the chunk's slice of A with contiguous loads, then
-// forms q for the chunk's (row, column) pairs from LDS.  Every row of p is
-// read from memory once per tile, every entry of A once per chunk.
+// Stand-alone outage-corrected product q = A_c p over many tiles.  The rows
+// are cut into chunks of ch and the chunks into segments of nseg; one
+// work-group streams one segment of one tile.  Its LDS holds a ring of
+// W = ch + 2 bw rows of p (the chunk and the band of A on either side) and
+// the chunk's slice of A.  While it forms q for chunk k from LDS, the loads
+// of chunk k + 1 (its ch new rows of p, its slice of A, its row pointers)
+// are in flight in registers; they are written to LDS once chunk k is done.
+// Work-groups are handed to the XCDs in turn (block b runs on XCD b mod 8);
+// the grid is numbered so that the segments of one tile follow each other
+// on one XCD, and the bw halo rows two segments share come from its L2.
 constexpr int kSpmmThreads = 256;
+constexpr int kXcds = 8;
+constexpr int kSpmmLoadsP = 8;  // 16-byte (8-byte when S = 1) loads of p per thread per chunk
+constexpr int kSpmmLoadsA = 8;  // entries of A per thread per chunk
+constexpr int kSpmmLoadsR = 2;  // row pointers per thread per chunk
+
+// a native two-double vector (kept in registers, unlike the HIP struct type)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 template <int S>
-__global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmParams p, int ring, int bw, double *partial) {
+struct SpmmStage {
+    using V = typename std::conditional<S % 2 == 0, dvec2, double>::type;
+    static constexpr int W = sizeof(V) / sizeof(double);
+    V vp[kSpmmLoadsP];
+    double va[kSpmmLoadsA];
+    int vc[kSpmmLoadsA], vr[kSpmmLoadsR], vpre[kSpmmLoadsR];
+    int lo = 0, np = 0;
+};
+
+// Issue the loads of p rows [lo, hi) and of chunk k's copy of A (entries,
+// row pointers, pre-order numbers).  None depends on another, so all are in
+// flight together and nothing waits on them until they are committed.
+template <int S>
+__device__ __forceinline__ void spmm_fetch(SpmmStage<S> &st, const SpmmParams &p, const double *P, int lo, int hi,
+                                           int k, int ch, int max_nnz, int tid, bool rows_only) {
+    using V = typename SpmmStage<S>::V;
+    const V *src = (const V *)(P + (size_t)lo * S);
+    st.lo = lo;
+    st.np = (hi - lo) * S / SpmmStage<S>::W;
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsP; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t < st.np) st.vp[j] = src[t];
+    }
+    if (rows_only) return;
+    const size_t e0 = (size_t)k * max_nnz;
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsA; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t < max_nnz) {
+            st.va[j] = p.c_val[e0 + t];
+            st.vc[j] = p.c_col[e0 + t];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsR; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t <= ch) st.vr[j] = p.c_rp[(size_t)k * (ch + 1) + t];
+        if (t < ch) st.vpre[j] = p.c_pre[(size_t)k * ch + t];
+    }
+}
+
+// Write fetched p rows into the ring and (unless rows_only) the chunk's A
+// into the chunk buffers, with the ring slot of every entry's column
+// resolved here once.  Row r lives in ring slot r mod Wr; base_slot is the
+// slot of the chunk's lowest read row, and every row the chunk touches lies
+// within Wr rows of it.
+template <int S>
+__device__ __forceinline__ void spmm_commit(const SpmmStage<S> &st, double *ring, double *lval, int *lcol, int *lrp,
+                                            int *lpre, int Wr, int lo_slot, int base_slot, int ch, int max_nnz,
+                                            int tid, bool rows_only) {
+    constexpr int VW = SpmmStage<S>::W;
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsP; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t < st.np) {
+            const int e = t * VW;  // first double of this load within the rows
+            int slot = lo_slot + e / S;
+            if (slot >= Wr) slot -= Wr;
+            *(typename SpmmStage<S>::V *)(ring + (size_t)slot * S + e % S) = st.vp[j];
+        }
+    }
+    if (rows_only) return;
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsA; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t < max_nnz) {
+            int slot = st.vc[j] + base_slot;
+            if (slot >= Wr) slot -= Wr;
+            lval[t] = st.va[j];
+            lcol[t] = slot * S;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSpmmLoadsR; ++j) {
+        const int t = j * kSpmmThreads + tid;
+        if (t <= ch) lrp[t] = st.vr[j];
+        if (t < ch) lpre[t] = st.vpre[j];
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kSpmmThreads)
+    spmm_kernel(SpmmParams p, int bw, int ch, int nseg, int n_segs, int max_nnz, double *partial) {
     extern __shared__ double lds[];
     constexpr int RS = kSpmmThreads / S;  // row slots
-    constexpr int CH = kSpmmChunk;
-    constexpr int NP = (CH * S + kSpmmThreads - 1) / kSpmmThreads;  // p doubles per thread per chunk
-    constexpr int NE = kSpmmMaxEnt / kSpmmThreads;                   // entries of A per thread per chunk
-    const int tile = blockIdx.x;
     const int tid = threadIdx.x;
     const int sc = tid % S, rs = tid / S;
+    const int n_tiles = p.ncols / S;
+    const int b = blockIdx.x;
+    const int tile = (b / kXcds / n_segs) * kXcds + b % kXcds;
+    const int seg = (b / kXcds) % n_segs;
+    if (tile >= n_tiles) return;  // whole work-group
     const int col = tile * S + sc;
     const int nr = p.n_r;
-    const int wm = ring - 1;
-    const size_t vs = (size_t)nr * S;
-    const double *P = p.p + (size_t)tile * vs;
-    double *Q = p.q + (size_t)tile * vs;
-    double *pr = lds;                                               // ring x S
-    double *lval = lds + (size_t)(ring > RS ? ring : RS) * S;  // chunk slice of A
-    int *lcol = (int *)(lval + kSpmmMaxEnt);
-    int *lrp = lcol + kSpmmMaxEnt;
+    const int Wr = ch + 2 * bw;  // ring rows
+    const int k0 = seg * nseg;
+    const int k1 = min((nr + ch - 1) / ch, k0 + nseg);
+    const double *P = p.p + (size_t)tile * nr * S;
+    double *Q = p.q + (size_t)tile * nr * S;
+    double *ring = lds;
+    double *lval = ring + (size_t)Wr * S;
+    int *lcol = (int *)(lval + max_nnz);
+    int *lrp = lcol + max_nnz;
+    int *lpre = lrp + ch + 1;
 
     const int c = p.outages[col];
     int ic = -1, jc = -1, lo = 0, hi = 0;
@@ -750,75 +296,49 @@ __global__ void __launch_bounds__(kSpmmThreads) spmm_kernel(SpmmParams p, int ri
     }
     const double dpc = ((ic >= 0) ? P[(size_t)ic * S + sc] : 0.0) - ((jc >= 0) ? P[(size_t)jc * S + sc] : 0.0);
 
-    // registers holding the next chunk's new p rows and slice of A
-    double rp[NP];
-    double rv[NE];
-    int rcol[NE], rrp = 0;
-    int ra = 0, rb = 0, re0 = 0, rne = 0;
-    auto fetch = [&](int c0) {  // loads for chunk c0: p rows [c0 + bw, c0 + CH + bw), A rows [c0, c0 + CH)
-        const int c1 = min(nr, c0 + CH);
-        ra = min(nr, max(0, c0 + bw));
-        rb = min(nr, c1 + bw);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int t = tid + k * kSpmmThreads;
-            rp[k] = (t < (rb - ra) * S) ? P[(size_t)ra * S + t] : 0.0;
+    // prologue: the rows before the first chunk's new rows, in passes
+    SpmmStage<S> st;
+    const int c0s = k0 * ch;
+    {
+        const int w0 = max(0, c0s - bw), w1 = min(nr, c0s + bw);
+        const int per = kSpmmLoadsP * kSpmmThreads * SpmmStage<S>::W / S;  // rows per pass
+        for (int r = w0; r < w1; r += per) {
+            spmm_fetch(st, p, P, r, min(w1, r + per), k0, ch, max_nnz, tid, true);
+            spmm_commit(st, ring, lval, lcol, lrp, lpre, Wr, r % Wr, 0, ch, max_nnz, tid, true);
         }
-        re0 = p.a_rowptr[c0];
-        rne = p.a_rowptr[c1] - re0;
-#pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            const int t = tid + k * kSpmmThreads;
-            rv[k] = (t < rne) ? p.a_val[re0 + t] : 0.0;
-            rcol[k] = (t < rne) ? p.a_col[re0 + t] : 0;
-        }
-        rrp = (tid <= c1 - c0) ? p.a_rowptr[c0 + tid] - re0 : 0;
-    };
-    auto commit = [&](int c0) {  // registers -> LDS
-        const int c1 = min(nr, c0 + CH);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int t = tid + k * kSpmmThreads;
-            if (t < (rb - ra) * S) pr[((ra + t / S) & wm) * S + t % S] = rp[k];
-        }
-#pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            const int t = tid + k * kSpmmThreads;
-            if (t < rne) {
-                lval[t] = rv[k];
-                lcol[t] = rcol[k] & wm;
-            }
-        }
-        if (tid <= c1 - c0) lrp[tid] = rrp;
-    };
-    // rows [0, bw) of p
-    for (int t = tid; t < min(bw, nr) * S; t += kSpmmThreads) pr[((t / S) & wm) * S + t % S] = P[t];
-    fetch(0);
+        spmm_fetch(st, p, P, w1, min(nr, c0s + ch + bw), k0, ch, max_nnz, tid, false);
+    }
     double pq = 0.0;
-    for (int c0 = 0; c0 < nr; c0 += CH) {
-        const int c1 = min(nr, c0 + CH);
-        commit(c0);
+    for (int k = k0; k < k1; ++k) {
+        const int c0 = k * ch, c1 = min(nr, c0 + ch);
+        const int base = max(0, c0 - bw);  // lowest row chunk k reads
+        const int bslot = base % Wr;
+        spmm_commit(st, ring, lval, lcol, lrp, lpre, Wr, st.lo % Wr, bslot, ch, max_nnz, tid, false);
         __syncthreads();
-        if (c1 < nr) fetch(c1);  // in flight while this chunk is formed
+        if (k + 1 < k1)
+            spmm_fetch(st, p, P, min(nr, c1 + bw), min(nr, c1 + ch + bw), k + 1, ch, max_nnz, tid, false);
         for (int i = c0 + rs; i < c1; i += RS) {
-            double q = 0.0;
             const int b0 = lrp[i - c0], b1 = lrp[i - c0 + 1];
-            for (int e = b0; e < b1; ++e) q += lval[e] * pr[lcol[e] * S + sc];
+            double q = 0.0;
+            for (int e = b0; e < b1; ++e) q += lval[e] * ring[lcol[e] + sc];
             if (i == ic) q -= bc * dpc;
             if (i == jc) q += bc * dpc;
-            if (in_interval(p.pre_row[i], lo, hi)) q = 0.0;
+            if (in_interval(lpre[i - c0], lo, hi)) q = 0.0;
             Q[(size_t)i * S + sc] = q;
-            pq += pr[(i & wm) * S + sc] * q;
+            int slot = bslot + (i - base);
+            if (slot >= Wr) slot -= Wr;
+            pq += ring[(size_t)slot * S + sc] * q;
         }
         __syncthreads();
     }
+    if (!partial) return;  // whole work-group
     // column sums of p'q over the row slots, in a fixed order
-    pr[tid] = pq;
+    ring[tid] = pq;
     __syncthreads();
     if (tid < S) {
         double a = 0.0;
-        for (int k = 0; k < RS; ++k) a += pr[k * S + sc];
-        if (partial) partial[col] = a;
+        for (int k = 0; k < RS; ++k) a += ring[k * S + sc];
+        partial[(size_t)seg * p.ncols + col] = a;
     }
 }
 
@@ -852,8 +372,8 @@ __global__ void order_inverse_kernel(int n, const int32_t *order, int32_t *pos) 
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n) pos[order[j]] = j;
 }
-
 }  // namespace
+
 
 size_t sort_temp_bytes(int n) {
     size_t bytes = 0;
@@ -873,37 +393,6 @@ hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(order_inverse_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, order, pos);
     return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
-constexpr int kPrefetchProd = 6;  // steps of prefetch in the product sweep
-
-template <int S>
-static hipError_t launch_pcg_s(const PcgParams &prm, int n_tiles, size_t lds, hipStream_t st) {
-    auto kern = pcg_tile_kernel<S, kPrefetch, kPrefetchProd>;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, prm);
-    return hipGetLastError();
-}
-
-hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
-    // ring rows plus the zero row and the trash row of idle slots
-    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
-    switch (S) {
-        case 1: return launch_pcg_s<1>(prm, n_tiles, lds, st);
-        case 2: return launch_pcg_s<2>(prm, n_tiles, lds, st);
-        case 4: return launch_pcg_s<4>(prm, n_tiles, lds, st);
-        case 8: return launch_pcg_s<8>(prm, n_tiles, lds, st);
-        case 16: return launch_pcg_s<16>(prm, n_tiles, lds, st);
-        case 32: return launch_pcg_s<32>(prm, n_tiles, lds, st);
-        case 64: return launch_pcg_s<64>(prm, n_tiles, lds, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st) {
@@ -935,41 +424,49 @@ hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st) {
     return hipGetLastError();
 }
 
-// ring rows: the chunk plus bw rows on either side, rounded up to a power of two
-int spmm_ring_rows(int bw) {
-    int W = 1;
-    while (W < kSpmmChunk + 2 * bw + 1) W <<= 1;
-    return W;
-}
-
 template <int S>
-static hipError_t launch_spmm_s(const SpmmParams &prm, int bw, int max_nnz, double *partial, hipStream_t st) {
+static hipError_t launch_spmm_s(const SpmmParams &prm, int bw, int ch, int nseg, int max_nnz, double *partial,
+                                hipStream_t st) {
     const int n_tiles = prm.ncols / S;
-    const int ring = spmm_ring_rows(bw);
-    const size_t lds = (size_t)std::max(ring, kSpmmThreads / S) * S * sizeof(double) +
-                       (size_t)kSpmmMaxEnt * (sizeof(double) + sizeof(int)) + (size_t)(kSpmmChunk + 1) * sizeof(int);
-    if (max_nnz > kSpmmMaxEnt) return hipErrorInvalidValue;
+    const int n_chunks = (prm.n_r + ch - 1) / ch;
+    const int n_segs = (n_chunks + nseg - 1) / nseg;
+    const size_t lds = spmm_lds_bytes(S, bw, ch, max_nnz);
     auto kern = spmm_kernel<S>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_tiles), dim3(kSpmmThreads), lds, st, prm, ring, bw, partial);
+    const int groups = (n_tiles + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(groups * kXcds * n_segs)), dim3(kSpmmThreads), lds, st, prm, bw, ch,
+                       nseg, n_segs, max_nnz, partial);
     if (partial && prm.pq)
-        hipLaunchKernelGGL(spmm_pq_reduce_kernel, dim3((prm.ncols + 255) / 256), dim3(256), 0, st, prm.ncols, 1,
-                           partial, prm.pq);
+        hipLaunchKernelGGL(spmm_pq_reduce_kernel, dim3((prm.ncols + 255) / 256), dim3(256), 0, st, prm.ncols,
+                           n_segs, partial, prm.pq);
     return hipGetLastError();
 }
 
-hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int max_nnz, double *partial, hipStream_t st) {
+size_t spmm_lds_bytes(int S, int bw, int ch, int max_nnz) {
+    return (size_t)(ch + 2 * bw) * S * sizeof(double) + (size_t)max_nnz * (sizeof(double) + sizeof(int)) +
+           (size_t)(2 * ch + 1) * sizeof(int);
+}
+
+bool spmm_chunk_fits(int S, int ch, int max_nnz) {
+    const int vw = (S % 2 == 0) ? 2 : 1;
+    return ch >= kSpmmThreads / S && ch % (kSpmmThreads / S) == 0 && ch * S <= kSpmmLoadsP * kSpmmThreads * vw &&
+           max_nnz <= kSpmmLoadsA * kSpmmThreads && ch + 1 <= kSpmmLoadsR * kSpmmThreads;
+}
+
+hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int ch, int nseg, int max_nnz, double *partial,
+                               hipStream_t st) {
+    if (!spmm_chunk_fits(S, ch, max_nnz) || nseg < 1) return hipErrorInvalidValue;
     switch (S) {
-        case 1: return launch_spmm_s<1>(prm, bw, max_nnz, partial, st);
-        case 2: return launch_spmm_s<2>(prm, bw, max_nnz, partial, st);
-        case 4: return launch_spmm_s<4>(prm, bw, max_nnz, partial, st);
-        case 8: return launch_spmm_s<8>(prm, bw, max_nnz, partial, st);
-        case 16: return launch_spmm_s<16>(prm, bw, max_nnz, partial, st);
-        case 32: return launch_spmm_s<32>(prm, bw, max_nnz, partial, st);
-        case 64: return launch_spmm_s<64>(prm, bw, max_nnz, partial, st);
+        case 1: return launch_spmm_s<1>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 2: return launch_spmm_s<2>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 4: return launch_spmm_s<4>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 8: return launch_spmm_s<8>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 16: return launch_spmm_s<16>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 32: return launch_spmm_s<32>(prm, bw, ch, nseg, max_nnz, partial, st);
+        case 64: return launch_spmm_s<64>(prm, bw, ch, nseg, max_nnz, partial, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,584 @@
+// The tile kernel of the batched "N-1" contingency PCG (gfx950, wave64, FP64).
+//
+// Layout.  Scenarios are grouped S to a tile; one wavefront owns one tile and
+// carries it through the whole preconditioned CG of Section III.A.  Its 64
+// lanes are R x S with R = 64 / S: lane = rs * S + sc treats scenario column
+// sc and row slot rs.  Per tile the workspace holds five vectors: delta (the
+// change of state from the base case), r, p, q = A_c p, and y / z (the
+// forward-solve result, overwritten by the backward-solve result), stored
+// one after the other, each (n_r + 1) x S row-major (row n_r is scratch), so
+// a wave touching a row of one vector reads S contiguous doubles and every
+// matrix entry it reads is shared by the S columns.
+//
+// The outage of branch c = (f, t) is applied as a rank-1 correction of the
+// shared base matrix: A_c = A - b_c u u^T with u = e_f - e_t (Section IV.B:
+// four entries change), so no per-scenario matrix exists.  Islanded buses
+// (a DFS pre-order interval of the bridge's far side) are held at zero.
+//
+// The triangular solves run through a schedule of steps of R independent
+// rows each; values the next rows depend on are kept in an LDS ring of
+// 2^k rows x S columns, sized on the host so that no live value is
+// overwritten.
+#include "gpcg_device.h"
+
+#include <climits>
+
+namespace gpcg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Sweeps.  Each sweep walks its program step by step through a three-stage
+// register pipeline: a step's row record is loaded H = 2D steps ahead, its
+// vector rows D steps ahead and its matrix entries E = 2 steps ahead (they
+// are shared by every wave and sit in L1/L2).  A step first consumes its
+// pipeline slots and then refills them with later steps, so no register is
+// copied, no load waits on another load still in flight, and a step only
+// waits on the LDS ring that carries the dependencies between rows.
+// Vector-memory counters complete in order, so the loop has no branches
+// around loads and stores: idle slots read and write the tile's scratch row
+// (row n_r) and the ring's trash row, and padding entries are real zero
+// entries in memory.
+//
+// A tile stores its five vectors one after the other, each row-major with
+// S columns: a wave's access to one vector row is S contiguous doubles, and
+// every sweep reads only the vectors it needs.  Vector bases are wave-uniform
+// (scalar registers); a step computes one 32-bit offset for all of them.
+enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
+constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
+constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
+
+// The step index as a vector register the compiler cannot see through.
+// Without it a wave-uniform index makes the loaded row id uniform too, and
+// the compiler copies it to a scalar register right after the load, which
+// waits for every load in flight.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ double ring_at(const double *ring, int byte_off) {
+    return *(const double *)((const char *)ring + byte_off);
+}
+
+__device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
+    *(double *)((char *)ring + byte_off) = v;
+}
+
+template <int K>
+struct Ents {
+    int3 e[K];
+};
+
+template <int S, int K>
+__device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, int rs) {
+    constexpr int R = kWave / S;
+    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
+    const int3 *base = g.ent + ((size_t)ss * K) * R + rs;
+#pragma unroll
+    for (int j = 0; j < K; ++j) E.e[j] = base[j * R];
+}
+
+// A step's ring values and entry values, gathered before the step's refill
+// loads are issued so that the LDS reads are in flight meanwhile.
+template <int K>
+struct Gath {
+    double r[K], v[K];
+};
+
+template <int K>
+__device__ __forceinline__ void gather(Gath<K> &G, const Ents<K> &E, const double *ring, int lane_off) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        G.r[j] = ring_at(ring, E.e[j].z + lane_off);
+        G.v[j] = __hiloint2double(E.e[j].y, E.e[j].x);
+    }
+}
+
+// sum_j v_j * ring[col_j]
+template <int K>
+__device__ __forceinline__ double gdot(const Gath<K> &G) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc += G.v[j] * G.r[j];
+    return acc;
+}
+
+// A tile's five vectors, each (n_r + 1) rows x S columns (row n_r is scratch).
+struct Tile {
+    double *v[kVectors];
+    int nr;
+};
+
+// byte offset of (row, column sc) inside any vector of a tile; idle slots
+// (row -1) go to the scratch row
+template <int S>
+__device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
+    return ((unsigned)(row >= 0 ? row : T.nr) * S + sc) * 8u;
+}
+
+__device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
+    return *(const double *)((const char *)T.v[v] + off);
+}
+
+__device__ __forceinline__ void vput(const Tile &T, int v, unsigned off, double x) {
+    *(double *)((char *)T.v[v] + off) = x;
+}
+
+// Programs end with kPadSteps idle steps, so reading past the last real step
+// only needs a clamp (no branch that would wait for the load).
+template <int S>
+__device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
+    constexpr int R = kWave / S;
+    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
+    return g.rec[ss * R + rs];
+}
+
+// ---- triangular sweeps -----------------------------------------------------
+// Consecutive steps of a triangular solve may depend on each other through
+// the ring, so a step is split in two.  Part A is the chain: finish the ring
+// dot product, form the row's value, write it to the ring and issue the next
+// step's ring reads.  Part B holds the rest of the step (stores, the next
+// step's right-hand side and carry, refills)
+// and is issued while those reads are in flight.  The right-hand side enters
+// as (rhs - carry) - dot, one subtraction on the chain.
+
+// ring byte addresses of a step's entries for this lane
+template <int K>
+__device__ __forceinline__ void ring_addr(int (&a)[K], const Ents<K> &E, int lane_off) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] = E.e[j].z + lane_off;
+}
+
+template <int K>
+__device__ __forceinline__ void ring_read(double (&r)[K], const int (&a)[K], const double *ring) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) r[j] = ring_at(ring, a[j]);
+}
+
+// sum_j v_j * ring[col_j] as a pairwise tree (short dependency chain)
+template <int K>
+__device__ __forceinline__ double tree_dot(const double (&r)[K], const Ents<K> &E) {
+    double acc[K / 2];
+#pragma unroll
+    for (int j = 0; j < K / 2; ++j)
+        acc[j] = __builtin_fma(__hiloint2double(E.e[2 * j + 1].y, E.e[2 * j + 1].x), r[2 * j + 1],
+                               __hiloint2double(E.e[2 * j].y, E.e[2 * j].x) * r[2 * j]);
+#pragma unroll
+    for (int w = 1; w < K / 2; w <<= 1)
+#pragma unroll
+        for (int j = 0; j + w < K / 2; j += 2 * w) acc[j] += acc[j + w];
+    return acc[0];
+}
+
+// ---- forward: r -= alpha q, ||r||^2, y = L^-1 r ---------------------------
+struct FwdVec {
+    double r, q;
+};
+
+template <int S>
+__device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
+    const unsigned o = row_off<S>(T, h.x, sc);
+    v.r = vget(T, VR, o);
+    v.q = vget(T, VQ, o);
+}
+
+template <int S, int D>
+__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                            double alpha) {
+    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
+    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rr = 0.0, carry = 0.0;
+    int4 hq[H];
+    FwdVec vq[D];
+    Ents<K> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double r = vq[0].r - alpha * vq[0].q;  // step 0's residual row
+    double rc = r;                         // ... minus its carry
+    fwd_vec<S>(vq[0], hq[D], T, sc);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            const int4 h = hq[d];
+            // A
+            const double dot = tree_dot(G, eq[d % E]);
+            const double y = rc - dot;
+            ring_put(ring, h.y + lane_off, y);
+            ring_addr(ga, eq[(d + 1) % E], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
+            {
+                const unsigned o = row_off<S>(T, h.x, sc);
+                vput(T, VR, o, r);
+                vput(T, VY, o, y);
+                rr += (h.x >= 0) ? r * r : 0.0;
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                const FwdVec v = vq[(d + 1) % D];
+                r = v.r - alpha * v.q;
+                rc = r - carry;
+            }
+            load_ents<S, K>(eq[d % E], g, s + E, rs);
+            fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            hq[d] = load_head<S>(g, s + H, rs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rr;
+}
+
+// ---- backward: z = U^-1 y, islanded rows zeroed on output, r'z ------------
+struct BwdVec {
+    double y, r, dinv;
+};
+
+template <int S>
+__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program &g, int s, int rs, const Tile &T,
+                                        int sc) {
+    constexpr int R = kWave / S;
+    const unsigned o = row_off<S>(T, h.x, sc);
+    v.y = vget(T, VY, o);
+    v.r = vget(T, VR, o);
+    v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
+}
+
+template <int S, int D>
+__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
+                                            int hi) {
+    constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
+    static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rz = 0.0, carry = 0.0;
+    int4 hq[H];
+    BwdVec vq[D];
+    Ents<K> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g, d, rs, T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double yc = vq[0].y, dv = vq[0].dinv, r = vq[0].r;  // step 0's row
+    bwd_vec<S>(vq[0], hq[D], g, D, rs, T, sc);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            const int4 h = hq[d];
+            // A
+            const double dot = tree_dot(G, eq[d % E]);
+            const double z = (yc - dot) * dv;
+            ring_put(ring, h.y + lane_off, z);
+            ring_addr(ga, eq[(d + 1) % E], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
+            {
+                const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
+                vput(T, VY, row_off<S>(T, h.x, sc), zm);
+                rz += (h.x >= 0) ? r * zm : 0.0;
+                carry = (h.w == 1) ? carry + dot : 0.0;
+                const BwdVec v = vq[(d + 1) % D];
+                yc = v.y - carry;
+                dv = v.dinv;
+                r = v.r;
+            }
+            load_ents<S, K>(eq[d % E], g, s + E, rs);
+            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g, s + 1 + D, rs, T, sc);
+            hq[d] = load_head<S>(g, s + H, rs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rz;
+}
+
+// ---- product: on the look-ahead row delta += alpha p_old and p = z + beta
+// p_old (into the ring and memory); on the current row q = A_c p from the
+// ring with the outaged branch shielded, and p'q.  Natural row order.
+struct ProdVec {
+    double z, p, x;
+};
+
+template <int S>
+__device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
+    const unsigned o = row_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
+    v.z = vget(T, VY, o);
+    v.p = vget(T, VP, o);
+    v.x = vget(T, VX, o);
+}
+
+template <int S, int D>
+__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                             double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
+                                             double bc) {
+    constexpr int H = 2 * D, E = kEntAheadProd;
+    const int lane_off = sc * 8;
+    const int wm = g.ring - 1;
+    const int zero = g.ring * S * 8;
+    const int trash = (g.ring + 1) * S * 8;
+    if (rs == 0) ring_put(ring, zero + lane_off, 0.0);
+    const int ic_off = ((ic >= 0) ? (ic & wm) * S * 8 : zero) + lane_off;
+    const int jc_off = ((jc >= 0) ? (jc & wm) * S * 8 : zero) + lane_off;
+    double pq = 0.0, carry = 0.0;
+    int4 hq[H];
+    ProdVec vq[D];
+    Ents<kEntProd> eq[E];
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+#pragma unroll
+    for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], g, d, rs);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int s = s0 + d;
+            const int4 h = hq[d];
+            const ProdVec v = vq[d % D];
+            // look-ahead row: pending solution update and new direction (its
+            // ring write must precede this step's reads)
+            const unsigned lo_ = row_off<S>(T, h.w, sc);
+            const double pn = done ? v.p : v.z + beta * v.p;
+            ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
+            Gath<kEntProd> G;
+            gather(G, eq[d % E], ring, lane_off);
+            const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
+            const double pown = ring_at(ring, h.y + lane_off);
+            prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
+            load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
+            hq[d] = load_head<S>(g, s + H, rs);
+            {
+                vput(T, VX, lo_, v.x + alpha * v.p);
+                vput(T, VP, lo_, pn);
+                const double dot = gdot(G);
+                double qv = carry + dot;
+                carry = (h.z == -2) ? carry + dot : 0.0;
+                const double dpc = pf - pt;
+                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
+                if (in_interval(h.z, lo, hi)) qv = 0.0;
+                vput(T, VQ, row_off<S>(T, h.x, sc), qv);
+                pq += (h.x >= 0) ? pown * qv : 0.0;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return pq;
+}
+
+// delta += alpha p over every row (the update the product sweep would have
+// made next, applied once the tile stops)
+template <int S>
+__device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, double alpha) {
+    constexpr int R = kWave / S;
+    for (int i = rs; i < T.nr; i += R) {
+        const unsigned o = row_off<S>(T, i, sc);
+        vput(T, VX, o, vget(T, VX, o) + alpha * vget(T, VP, o));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile kernel: init, then PCG iterations until every column stops.
+template <int S, int D, int DP>
+__global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
+    constexpr int R = kWave / S;
+    extern __shared__ double ring[];
+    const int lane = threadIdx.x;
+    const int sc = lane % S;
+    const int rs = lane / S;
+    const int tile = blockIdx.x + p.tile0;
+    const int posn = tile * S + sc;  // tile position of this column
+    const bool valid = posn < p.n_out;
+    const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
+    const int nr = p.n_r;
+    Tile T;
+    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * (nr + 1) * S;
+    T.nr = nr;
+
+    // ---- per-column outage data -------------------------------------------
+    int c = valid ? p.outages[scen] : -1;
+    const bool bad = valid && (c < -1 || c >= p.m);
+    if (bad) c = -1;
+    int ic = -1, jc = -1, lo = 0, hi = 0;
+    double bc = 0.0;
+    if (c >= 0) {
+        ic = p.br_from[c] - 1;
+        jc = p.br_to[c] - 1;
+        bc = p.br_b[c];
+        lo = p.isl_lo[c];
+        hi = p.isl_hi[c];
+    }
+    if (bad) {
+        lo = 0;
+        hi = INT_MAX;
+    }
+    const bool island = hi > lo;
+
+    // ---- re-dispatch (Section IV.C): islanded power over main generators --
+    double dP = 0.0, Sg = 0.0;
+    for (int i = rs; i < nr; i += R) {
+        const double Pk = p.rhs[i + 1];
+        if (in_interval(p.pre_row[i], lo, hi))
+            dP += Pk;
+        else if (Pk > 0.0)
+            Sg += Pk;
+    }
+    dP = col_sum<S>(dP);
+    Sg = col_sum<S>(Sg);
+    const bool nogen = island && !(Sg > 0.0);
+    const double gfac = (p.kind == 0 && island && !bad && !nogen) ? dP / Sg : 0.0;
+
+    // ---- correction-form start from the base state --------------------------
+    // r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
+    const double thf = (ic >= 0) ? p.theta_b[ic + 1] : 0.0;
+    const double tht = (jc >= 0) ? p.theta_b[jc + 1] : 0.0;
+    const double corr = bc * (thf - tht);
+    double rr = 0.0, bb = 0.0;
+    for (int i = rs; i < nr; i += R) {
+        double r0 = 0.0;
+        if (!in_interval(p.pre_row[i], lo, hi)) {
+            const double Pk = p.rhs[i + 1];
+            const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
+            r0 = dPk + p.rho_b[i];
+            if (i == ic) r0 += corr;
+            if (i == jc) r0 -= corr;
+            const double b = Pk + dPk;
+            bb += b * b;
+        }
+        rr += r0 * r0;
+        const unsigned o = row_off<S>(T, i, sc);
+        vput(T, VX, o, 0.0);
+        vput(T, VR, o, r0);
+        vput(T, VP, o, 0.0);
+        vput(T, VQ, o, 0.0);
+    }
+    if (rs == 0) {
+        const unsigned o = row_off<S>(T, nr, sc);
+        for (int v = 0; v < kVectors; ++v) vput(T, v, o, 0.0);
+    }
+    rr = col_sum<S>(rr);
+    bb = col_sum<S>(bb);
+
+    int status = kConverged;
+    int iters = 0;
+    bool done;
+    if (!valid) {
+        done = true;
+    } else if (bad) {
+        done = true;
+        status = kBadOutage;
+    } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(bb)) {
+        done = true;
+        status = kNonfinite;
+    } else {
+        done = rr <= p.tol2 * bb;
+    }
+    __syncthreads();
+
+    double alpha = 0.0, rho = 0.0;
+    for (int k = 0;; ++k) {
+        // ---- forward sweep: delta += alpha p, r -= alpha q, y = L^-1 r ----
+        double rrp = fwd_sweep<S, D>(p.fwd, ring, T, rs, sc, alpha);
+        __syncthreads();
+        rrp = col_sum<S>(rrp);
+        if (k > 0 && !done) {
+            iters = k;
+            if (!__builtin_isfinite(rrp)) {
+                done = true;
+                status = kNonfinite;
+            } else if (rrp <= p.tol2 * bb) {
+                done = true;
+            }
+        }
+        if (k >= p.max_iter && !done) {
+            status = kMaxIter;
+            done = true;
+        }
+        if (__all(done)) {
+            // the last step length has not reached delta yet
+            final_update<S>(T, rs, sc, alpha);
+            break;
+        }
+
+        // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
+        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, lo, hi));
+        __syncthreads();
+        const double beta = (k == 0 || done) ? 0.0 : rz / rho;
+        rho = rz;
+
+        // ---- p = z + beta p and q = A_c p (outaged branch shielded), p'q ---
+        const double sigma =
+            col_sum<S>(prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc));
+        __syncthreads();
+        if (!done) {
+            if (!__builtin_isfinite(sigma) || !__builtin_isfinite(rho)) {
+                done = true;
+                status = kNonfinite;
+            } else if (!(sigma > 0.0)) {
+                done = true;
+                status = kBreakdown;
+            } else {
+                alpha = rho / sigma;
+            }
+        }
+        if (done) alpha = 0.0;
+    }
+
+    if (valid && rs == 0) {
+        int st = status;
+        if (st == kConverged && island) st = (p.kind == 0 && nogen) ? kIslandedNoGen : kConvergedIslanded;
+        p.iters_out[scen] = iters;
+        p.status_out[scen] = st;
+        p.gfac_out[scen] = gfac;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
+constexpr int kPrefetchProd = 6;  // steps of prefetch in the product sweep
+
+template <int S>
+static hipError_t launch_pcg_s(const PcgParams &prm, int n_tiles, size_t lds, hipStream_t st) {
+    auto kern = pcg_tile_kernel<S, kPrefetch, kPrefetchProd>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    // ring rows plus the zero row and the trash row of idle slots
+    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
+    switch (S) {
+        case 1: return launch_pcg_s<1>(prm, n_tiles, lds, st);
+        case 2: return launch_pcg_s<2>(prm, n_tiles, lds, st);
+        case 4: return launch_pcg_s<4>(prm, n_tiles, lds, st);
+        case 8: return launch_pcg_s<8>(prm, n_tiles, lds, st);
+        case 16: return launch_pcg_s<16>(prm, n_tiles, lds, st);
+        case 32: return launch_pcg_s<32>(prm, n_tiles, lds, st);
+        case 64: return launch_pcg_s<64>(prm, n_tiles, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gpcg
