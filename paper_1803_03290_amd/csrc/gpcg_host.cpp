@@ -1100,7 +1100,27 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
         s.p = p;
         s.q = q;
         s.pq = pq;
-        const int nseg = std::min(n_chunks, 8);
+        // Segment length: the grid runs in rounds of `slots` resident
+        // work-groups (LDS-bound, at most four of 256 threads per CU), and a
+        // work-group costs its chunks plus a prologue of about 2 bw rows;
+        // take the length with the fewest chunk-times over all rounds.
+        int cu = 256;
+        (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device);
+        const size_t lds = gpcg::spmm_lds_bytes(S, bw, ch, max_nnz);
+        const long slots = (long)cu * std::max<long>(1, std::min<long>(4, (long)(160 * 1024) / (long)lds));
+        const long tile_slots = ((ncols / S) + 7) / 8 * 8;  // the grid pads tiles to whole XCD rounds
+        int nseg = 1;
+        double best = 1e300;
+        for (int cand = 1; cand <= n_chunks; ++cand) {
+            const long segs = (n_chunks + cand - 1) / cand;
+            if (cand > 1 && (n_chunks + cand - 2) / (cand - 1) == segs) continue;  // same split as cand - 1
+            const long rounds = (tile_slots * segs + slots - 1) / slots;
+            const double cost = (double)rounds * (cand + 2.0 * bw / ch);
+            if (cost < best) {
+                best = cost;
+                nseg = cand;
+            }
+        }
         double *partial = nullptr;
         if (pq) {
             const size_t need = (size_t)((n_chunks + nseg - 1) / nseg) * ncols;

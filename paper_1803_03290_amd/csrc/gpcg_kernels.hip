@@ -200,7 +200,7 @@ __device__ __forceinline__ void spmm_fetch(SpmmStage<S> &st, const SpmmParams &p
 #pragma unroll
     for (int j = 0; j < kSpmmLoadsP; ++j) {
         const int t = j * kSpmmThreads + tid;
-        if (t < st.np) st.vp[j] = src[t];
+        if (t < st.np) st.vp[j] = __builtin_nontemporal_load(&src[t]);  // streamed once
     }
     if (rows_only) return;
     const size_t e0 = (size_t)k * max_nnz;
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kSpmmThreads)
             if (i == ic) q -= bc * dpc;
             if (i == jc) q += bc * dpc;
             if (in_interval(lpre[i - c0], lo, hi)) q = 0.0;
-            Q[(size_t)i * S + sc] = q;
+            __builtin_nontemporal_store(q, &Q[(size_t)i * S + sc]);  // q is not read back here
             int slot = bslot + (i - base);
             if (slot >= Wr) slot -= Wr;
             pq += ring[(size_t)slot * S + sc] * q;

@@ -233,3 +233,38 @@ def test_bpp_context(gp, grids):
         np.testing.assert_array_equal(res["island"][s].astype(bool), d["island"])
         exp = 0 if not d["island"].any() else gp.CONVERGED_ISLANDED
         assert res["status"][s] == exp
+
+
+# ------------------------------------------- stand-alone product, full size
+
+
+def test_spmm_grid10k_full_launch_sampled(gp, grids):
+    """The product as the benchmark times it: every outage column of the
+    10,000-bus grid in one launch at block 32, p ~ N(0, 1); 64 seeded columns
+    checked against the oracle's explicit A_c (islanded rows zero) and their
+    p'q."""
+    g = grids["grid10k"]
+    _, A = oracle.base_case(g)
+    S = 32
+    ctx = _ctx(gp, g, block=S)
+    nr = g.n - 1
+    ncols = ((g.m + S - 1) // S) * S
+    outs = np.arange(ncols) % g.m
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    p = torch.randn((ncols // S, nr, S), dtype=torch.float64, device="cuda", generator=gen)
+    q = torch.empty_like(p)
+    pq = torch.empty(ncols, dtype=torch.float64, device="cuda")
+    ctx.spmm(torch.tensor(outs.astype(np.int32), device="cuda"), p, q, pq)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(ncols, 64, replace=False))
+    pqh = pq.cpu().numpy()
+    for j in sample:
+        pj = p[j // S, :, j % S].cpu().numpy()
+        qj = q[j // S, :, j % S].cpu().numpy()
+        c = int(outs[j])
+        keep = ~oracle.island_of(g, c)[1:]
+        expect = np.where(keep, oracle.outage_matrix(g, A, c) @ pj, 0.0)
+        np.testing.assert_allclose(qj, expect, rtol=1e-13, atol=1e-9)
+        assert pqh[j] == pytest.approx(float(pj @ expect), rel=1e-11)
