@@ -215,6 +215,28 @@ int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, co
                              int32_t *status_out, uint8_t *island_out, double *resid_out);
 
 /*
+ * The batched solve with a right-hand side of its own for every scenario,
+ * as the adjoint of a screening loss and the half-iterations of the
+ * fast-decoupled power flow need (Section III: eqs. (4)-(5) solved for a
+ * given mismatch; adjoint systems for the gradients).  Scenario j solves
+ * A_c[M,M] x_M = b_j|M by the same batched PCG with the base-case ILU(0)
+ * preconditioner, starting from x = 0; there is no base state and no
+ * re-dispatch, islanded buses and the slack get x = 0.
+ *   rhs_cols   device f64[n_out * ld], b_j at rhs_cols + j * ld indexed by
+ *              bus (the slack's entry is ignored); ld >= n_bus.
+ *   x_out      device f64[n_out * n_bus] (scenario-major).
+ *   iters_out, status_out, island_out (nullable), resid_out (nullable,
+ *              ||b_M - A_c x_M|| / ||b_M|| in double-double): as for
+ *              gpcg_solve_contingencies; an islanding outage reports
+ *              GPCG_CONVERGED_ISLANDED (never GPCG_ISLANDED_NO_GEN).
+ * Errors: GPCG_E_ARG for NULL pointers, ld < n_bus, max_iter < 1 or a bad
+ * tol.  Asynchronous on the context's stream, like the other solves.
+ */
+int gpcg_solve_rhs(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs_cols, int32_t ld, double tol,
+                   int32_t max_iter, double *x_out, int32_t *iters_out, int32_t *status_out, uint8_t *island_out,
+                   double *resid_out);
+
+/*
  * The same computation with the plain per-scenario PCG: one scenario at a
  * time (S = 1), each as its own launch in the context's stream, with the
  * wavefront's 64 lanes spread over rows instead of scenarios.  Same

@@ -61,6 +61,8 @@ SIGNATURES = {
     "gpcg_solve_contingencies": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
                                            _VP, _VP]),
     "gpcg_solve_plain": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_solve_rhs": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
+                                 _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "gpcg_get_order": (C.c_int, [_VP, C.c_int32, _i32p]),
     "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
@@ -251,6 +253,28 @@ class Context:
         _check(fn(self._h, n_out, _ptr(outages), _ptr(rhs), float(tol), int(max_iter), _ptr(out["x"]),
                   _ptr(out["flows"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["island"]),
                   _ptr(out["resid"])))
+        return out
+
+    def solve_rhs(self, outages, rhs_cols, tol=1e-12, max_iter=20000, *, island=False, resid=True, x=None):
+        """gpcg_solve_rhs: scenario j solves A_c x = rhs_cols[j] (device
+        float64[n_out, ld], ld >= n_bus) from x = 0.  Returns the dict of
+        device tensors x, iters, status, island, resid."""
+        import torch
+
+        n_out = int(outages.shape[0])
+        if rhs_cols.dim() != 2 or rhs_cols.shape[0] != n_out or rhs_cols.stride(1) != 1:
+            raise ValueError("rhs_cols must be a row-major [n_out, ld] tensor")
+        dev = outages.device
+        out = {
+            "x": x if x is not None else torch.empty((n_out, self.n_bus), dtype=torch.float64, device=dev),
+            "iters": torch.empty(n_out, dtype=torch.int32, device=dev),
+            "status": torch.empty(n_out, dtype=torch.int32, device=dev),
+            "island": torch.empty((n_out, self.n_bus), dtype=torch.uint8, device=dev) if island else None,
+            "resid": torch.empty(n_out, dtype=torch.float64, device=dev) if resid else None,
+        }
+        _check(self._lib.gpcg_solve_rhs(self._h, n_out, _ptr(outages), _ptr(rhs_cols), int(rhs_cols.stride(0)),
+                                        float(tol), int(max_iter), _ptr(out["x"]), _ptr(out["iters"]),
+                                        _ptr(out["status"]), _ptr(out["island"]), _ptr(out["resid"])))
         return out
 
     def order(self, n_out) -> np.ndarray:

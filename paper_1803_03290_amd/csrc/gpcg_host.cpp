@@ -613,11 +613,14 @@ namespace {
 
 void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const double *rhs, double tol,
                int max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
-               uint8_t *island_out, double *resid_out) {
+               uint8_t *island_out, double *resid_out, const double *rhs_cols = nullptr, int rhs_ld = 0) {
     if (!h) fail(GPCG_E_ARG, "context is NULL");
     if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
     if (n_out == 0) return;
-    if (!outages || !rhs || !x_out || !iters_out || !status_out) fail(GPCG_E_ARG, "a required pointer is NULL");
+    if (!outages || !(rhs || rhs_cols) || !x_out || !iters_out || !status_out)
+        fail(GPCG_E_ARG, "a required pointer is NULL");
+    if (rhs_cols && rhs_ld < h->n_bus) fail(GPCG_E_ARG, "ld must be >= n_bus");
+    if (rhs_cols && flows_out) fail(GPCG_E_ARG, "flows are not formed for per-scenario right-hand sides");
     if (max_iter < 1) fail(GPCG_E_ARG, "max_iter must be >= 1");
     if (!(tol >= 0.0) || !std::isfinite(tol)) fail(GPCG_E_ARG, "tol must be finite and >= 0");
     if (flows_out && h->kind != GPCG_KIND_BP) fail(GPCG_E_ARG, "flows are only defined for a B' context");
@@ -625,10 +628,13 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     DevSchedule &D = h->schedule_for(S_);
     h->ensure_workspace(n_out, S_);
     // residual of the base state for this right-hand side, in double-double
-    hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
-                                         h->rho_b.p, h->stream),
-              "base residual");
+    if (!rhs_cols)
+        hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
+                                             h->rho_b.p, h->stream),
+                  "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
+    p.rhs_cols = rhs_cols;
+    p.rhs_ld = rhs_ld;
     const int32_t *pos = nullptr;
     if (S_ > 1 && n_out > S_) {
         // group scenarios of similar expected work into the same tiles
@@ -685,6 +691,8 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.isl_hi = h->isl_hi.p;
     o.theta_b = h->theta_b.p;
     o.rhs = rhs;
+    o.rhs_cols = rhs_cols;
+    o.rhs_ld = rhs_ld;
     o.outages = outages;
     o.pos = pos;
     o.ws = h->ws.p;
@@ -985,6 +993,17 @@ int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, co
         if (!h) fail(GPCG_E_ARG, "context is NULL");
         run_solve(h, h->S, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
                   resid_out);
+    });
+}
+
+int gpcg_solve_rhs(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs_cols, int32_t ld, double tol,
+                   int32_t max_iter, double *x_out, int32_t *iters_out, int32_t *status_out, uint8_t *island_out,
+                   double *resid_out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        if (!rhs_cols) fail(GPCG_E_ARG, "rhs_cols is NULL");
+        run_solve(h, h->S, n_out, outages, nullptr, tol, max_iter, x_out, nullptr, iters_out, status_out, island_out,
+                  resid_out, rhs_cols, ld);
     });
 }
 

@@ -68,6 +68,11 @@ struct PcgParams {
     const double *theta_b;  // n_bus, slack 0
     const double *rho_b;    // n_r: rhs - A theta_b
     const double *rhs;      // n_bus
+    // per-scenario right-hand sides (NULL: rhs above with the warm start):
+    // scenario j solves A_c x = rhs_cols[j * rhs_ld + bus] from x = 0, with
+    // no re-dispatch
+    const double *rhs_cols;
+    int rhs_ld;
     // scenarios: tile position j solves scenario order[j] (NULL: j itself)
     const int32_t *outages;
     const int32_t *order;
@@ -89,6 +94,8 @@ struct OutParams {
     const int32_t *pre_bus;  // n_bus
     const int32_t *isl_lo, *isl_hi;
     const double *theta_b, *rhs;
+    const double *rhs_cols;  // per-scenario right-hand sides (then x = delta, no base state added)
+    int rhs_ld;
     const int32_t *outages;
     const int32_t *pos;  // tile position of each scenario (NULL: the scenario index)
     const double *ws;

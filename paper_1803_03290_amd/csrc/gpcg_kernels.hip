@@ -51,7 +51,7 @@ __global__ void theta_out_kernel(OutParams p) {
     if (k > 0 && !in && !bad) {
         const int j = p.pos ? p.pos[s] : s;
         const int tile = j / p.S, sc = j % p.S;
-        th = p.theta_b[k] + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
+        th = (p.rhs_cols ? 0.0 : p.theta_b[k]) + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
     }
     p.x_out[(size_t)s * p.n_bus + k] = th;
     if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
@@ -71,7 +71,8 @@ __global__ void flows_out_kernel(OutParams p) {
 }
 
 // True relative residual ||P'_M - A_c theta_M|| / ||P'_M|| of the returned
-// angles, each row's residual formed in double-double.
+// angles (or ||b_M - A_c x_M|| / ||b_M|| for per-scenario right-hand sides),
+// each row's residual formed in double-double.
 __global__ void __launch_bounds__(256) resid_kernel(OutParams p) {
     __shared__ double sh_r[256], sh_b[256];
     const int s = blockIdx.x;
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) resid_kernel(OutParams p) {
     if (!bad) {
         for (int i = threadIdx.x; i < p.n_r; i += blockDim.x) {
             if (in_interval(p.pre_bus[i + 1], lo, hi)) continue;
-            const double Pk = p.rhs[i + 1];
+            const double Pk = p.rhs_cols ? p.rhs_cols[(size_t)s * p.rhs_ld + i + 1] : p.rhs[i + 1];
             const double b = Pk + ((gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0);
             double h = b, l = 0.0;
             for (int e = p.a_rowptr[i]; e < p.a_rowptr[i + 1]; ++e) dd_fma(h, l, -p.a_val[e], th[p.a_col[e] + 1]);

@@ -429,43 +429,60 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     }
     const bool island = hi > lo;
 
-    // ---- re-dispatch (Section IV.C): islanded power over main generators --
-    double dP = 0.0, Sg = 0.0;
-    for (int i = rs; i < nr; i += R) {
-        const double Pk = p.rhs[i + 1];
-        if (in_interval(p.pre_row[i], lo, hi))
-            dP += Pk;
-        else if (Pk > 0.0)
-            Sg += Pk;
-    }
-    dP = col_sum<S>(dP);
-    Sg = col_sum<S>(Sg);
-    const bool nogen = island && !(Sg > 0.0);
-    const double gfac = (p.kind == 0 && island && !bad && !nogen) ? dP / Sg : 0.0;
-
-    // ---- correction-form start from the base state --------------------------
-    // r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
-    const double thf = (ic >= 0) ? p.theta_b[ic + 1] : 0.0;
-    const double tht = (jc >= 0) ? p.theta_b[jc + 1] : 0.0;
-    const double corr = bc * (thf - tht);
-    double rr = 0.0, bb = 0.0;
-    for (int i = rs; i < nr; i += R) {
-        double r0 = 0.0;
-        if (!in_interval(p.pre_row[i], lo, hi)) {
-            const double Pk = p.rhs[i + 1];
-            const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
-            r0 = dPk + p.rho_b[i];
-            if (i == ic) r0 += corr;
-            if (i == jc) r0 -= corr;
-            const double b = Pk + dPk;
-            bb += b * b;
+    const bool cols = p.rhs_cols != nullptr;
+    double rr = 0.0, bb = 0.0, gfac = 0.0;
+    bool nogen = false;
+    if (cols) {
+        // ---- per-scenario right-hand side, zero start: r0 = b restricted to M
+        const double *b = p.rhs_cols + (size_t)(valid ? scen : 0) * p.rhs_ld + 1;
+        for (int i = rs; i < nr; i += R) {
+            const double r0 = (valid && !in_interval(p.pre_row[i], lo, hi)) ? b[i] : 0.0;
+            rr += r0 * r0;
+            const unsigned o = row_off<S>(T, i, sc);
+            vput(T, VX, o, 0.0);
+            vput(T, VR, o, r0);
+            vput(T, VP, o, 0.0);
+            vput(T, VQ, o, 0.0);
         }
-        rr += r0 * r0;
-        const unsigned o = row_off<S>(T, i, sc);
-        vput(T, VX, o, 0.0);
-        vput(T, VR, o, r0);
-        vput(T, VP, o, 0.0);
-        vput(T, VQ, o, 0.0);
+        bb = rr;
+    } else {
+        // ---- re-dispatch (Section IV.C): islanded power over main generators
+        double dP = 0.0, Sg = 0.0;
+        for (int i = rs; i < nr; i += R) {
+            const double Pk = p.rhs[i + 1];
+            if (in_interval(p.pre_row[i], lo, hi))
+                dP += Pk;
+            else if (Pk > 0.0)
+                Sg += Pk;
+        }
+        dP = col_sum<S>(dP);
+        Sg = col_sum<S>(Sg);
+        nogen = island && !(Sg > 0.0);
+        gfac = (p.kind == 0 && island && !bad && !nogen) ? dP / Sg : 0.0;
+
+        // ---- correction-form start from the base state ----------------------
+        // r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
+        const double thf = (ic >= 0) ? p.theta_b[ic + 1] : 0.0;
+        const double tht = (jc >= 0) ? p.theta_b[jc + 1] : 0.0;
+        const double corr = bc * (thf - tht);
+        for (int i = rs; i < nr; i += R) {
+            double r0 = 0.0;
+            if (!in_interval(p.pre_row[i], lo, hi)) {
+                const double Pk = p.rhs[i + 1];
+                const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
+                r0 = dPk + p.rho_b[i];
+                if (i == ic) r0 += corr;
+                if (i == jc) r0 -= corr;
+                const double b = Pk + dPk;
+                bb += b * b;
+            }
+            rr += r0 * r0;
+            const unsigned o = row_off<S>(T, i, sc);
+            vput(T, VX, o, 0.0);
+            vput(T, VR, o, r0);
+            vput(T, VP, o, 0.0);
+            vput(T, VQ, o, 0.0);
+        }
     }
     if (rs == 0) {
         const unsigned o = row_off<S>(T, nr, sc);

@@ -268,3 +268,64 @@ def test_spmm_grid10k_full_launch_sampled(gp, grids):
         expect = np.where(keep, oracle.outage_matrix(g, A, c) @ pj, 0.0)
         np.testing.assert_allclose(qj, expect, rtol=1e-13, atol=1e-9)
         assert pqh[j] == pytest.approx(float(pj @ expect), rel=1e-11)
+
+
+# ------------------------------------- per-scenario right-hand sides
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_solve_rhs_grid200(gp, grids, kind):
+    """Every outage (and the base case) with its own seeded right-hand side,
+    B' and B'' (with shunts), ld > n_bus: x against the oracle's direct solve
+    of A_c[M,M] x = b_M (no re-dispatch), iterations against the textbook
+    PCG from x = 0 on the same factors."""
+    g = grids["grid200"]
+    shunt = np.random.default_rng(3).uniform(0, 0.05, g.n) if kind == 1 else None
+    _, A = oracle.base_case(g, shunt=shunt)
+    L, U = oracle.ilu0(A)
+    ctx = _ctx(gp, g, block=16, kind=kind, shunt=shunt)
+    outs = np.arange(-1, g.m)
+    rng = np.random.default_rng(21 + kind)
+    Bw = rng.normal(0, 0.5, (len(outs), g.n + 3))
+    res = ctx.solve_rhs(torch.tensor(outs.astype(np.int32), device="cuda"), torch.tensor(Bw, device="cuda"),
+                        tol=1e-12, island=True)
+    torch.cuda.synchronize()
+    x = res["x"].cpu().numpy()
+    st = res["status"].cpu().numpy()
+    it = res["iters"].cpu().numpy()
+    isl = res["island"].cpu().numpy().astype(bool)
+    rs = res["resid"].cpu().numpy()
+    for s, c in enumerate(outs):
+        b = Bw[s, :g.n]
+        d = oracle.scenario(g, int(c), A, rhs=b, redispatch_islands=False, shunt=shunt)
+        assert np.abs(x[s] - d["theta"]).max() <= ANGLE_TOL, (c, np.abs(x[s] - d["theta"]).max())
+        np.testing.assert_array_equal(isl[s], d["island"])
+        assert st[s] == (gp.CONVERGED_ISLANDED if d["island"].any() else 0), (c, st[s])
+        assert rs[s] <= RESID_TOL, (c, rs[s])
+        if s % 7 == 0:
+            mask = ~d["island"][1:]
+            Ac = oracle.outage_matrix(g, A, int(c))
+            _, k, _, _ = oracle.pcg_textbook(Ac, np.where(mask, b[1:], 0.0), L, U, mask=mask, tol=1e-12)
+            assert _iters_close(it[s], k), (c, it[s], k)
+
+
+def test_solve_rhs_edges(gp, grids):
+    """A zero right-hand side (x = 0 in no iterations), a ragged batch of 70,
+    bad outage ids, and the rhs argument checks."""
+    g = grids["grid200"]
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=64)
+    outs = np.array([5, g.m, -9] + list(range(67)), np.int32)
+    B = np.random.default_rng(2).normal(0, 0.5, (len(outs), g.n))
+    B[0] = 0.0
+    res = ctx.solve_rhs(torch.tensor(outs, device="cuda"), torch.tensor(B, device="cuda"))
+    torch.cuda.synchronize()
+    x = res["x"].cpu().numpy()
+    st = res["status"].cpu().numpy()
+    assert np.all(x[0] == 0.0) and res["iters"][0].item() == 0
+    assert st[1] == gp.BAD_OUTAGE and st[2] == gp.BAD_OUTAGE and np.all(x[1:3] == 0.0)
+    for s in range(3, len(outs)):
+        d = oracle.scenario(g, int(outs[s]), A, rhs=B[s], redispatch_islands=False)
+        assert np.abs(x[s] - d["theta"]).max() <= ANGLE_TOL
+    with pytest.raises(gp.GpcgError):
+        ctx.solve_rhs(torch.tensor(outs, device="cuda"), torch.tensor(B[:, :-1].copy(), device="cuda"))
