@@ -237,6 +237,48 @@ int gpcg_solve_rhs(gpcg_t h, int32_t n_out, const int32_t *outages, const double
                    double *resid_out);
 
 /*
+ * Smooth branch-overload screening loss of every outage and its gradients
+ * by the adjoint method.  The screening quantity is the post-outage branch
+ * flow (Section IV: flows of the re-dispatched solution); per scenario
+ *     L = sum_e softplus(kappa (|f_e| / F_e - 1)),
+ * with caller-given limits F_e (held constant).  The gradients with respect
+ * to the bus injections P and the branch reactances x come from one adjoint
+ * solve per scenario, A_c[M,M] lambda_M = (dL/dtheta)_M, run by the same
+ * batched PCG with the same symmetric base-case ILU(0) preconditioner; the
+ * forward angles are recomputed by this call (no iterate is stored).
+ *   dL/dx_e = -s_e f_e / x_e + (lambda_f - lambda_t)(theta_f - theta_t) / x_e^2
+ *             (s_e = dL/df_e; 0 for the outaged branch),
+ *   dL/dP   = (dP'/dP)^T lambda through the re-dispatch of Section IV.C
+ *             (0 for the slack's injection).
+ * At f_e = 0 the derivative of |f_e| is taken as 0.
+ *   rhs          device f64[n_bus]: injections P (slack entry ignored).
+ *   flow_limit   device f64[m]: F_e > 0.
+ *   loss_out     device f64[n_out].
+ *   grad_p_out   device f64[n_out * n_bus] or NULL; grad_x_out device
+ *                f64[n_out * m] or NULL (both NULL: loss only, no adjoint).
+ *   iters_out, status_out  device int32[2 * n_out]: the forward solve's in
+ *                the first n_out, the adjoint solve's in the next n_out
+ *                (written only when a gradient is asked for).
+ * The context must be a B' context built with these reactances.  Errors:
+ * GPCG_E_ARG for NULL pointers, a B'' context or kappa <= 0.  Asynchronous
+ * on the context's stream; the workspace (four n_out x n_bus or n_out x m
+ * f64 arrays) is kept by the context.
+ */
+int gpcg_overload_gradients(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs,
+                            const double *flow_limit, double kappa, double tol, int32_t max_iter, double *loss_out,
+                            double *grad_p_out, double *grad_x_out, int32_t *iters_out, int32_t *status_out);
+
+/*
+ * out[j] = sum_r w[r] a[r * lda + j] on the context's stream, rows summed in
+ * order: the weighted sum of per-scenario gradient rows that a caller's
+ * reverse-mode differentiation needs (not a step of the paper's method).
+ * a: device f64[n_rows * lda], lda >= n_cols; w: device f64[n_rows];
+ * out: device f64[n_cols].  GPCG_E_ARG for bad sizes or NULL pointers.
+ */
+int gpcg_weighted_rows(gpcg_t h, int32_t n_rows, int32_t n_cols, const double *a, int32_t lda, const double *w,
+                       double *out);
+
+/*
  * The same computation with the plain per-scenario PCG: one scenario at a
  * time (S = 1), each as its own launch in the context's stream, with the
  * wavefront's 64 lanes spread over rows instead of scenarios.  Same

@@ -24,3 +24,4 @@ from .binding import (  # noqa: F401
     lib,
     topology,
 )
+from .overload import OverloadLoss, overload_loss  # noqa: F401,E402

@@ -63,6 +63,9 @@ SIGNATURES = {
     "gpcg_solve_plain": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "gpcg_solve_rhs": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
                                  _VP]),
+    "gpcg_overload_gradients": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double, C.c_double, C.c_int32, _VP,
+                                          _VP, _VP, _VP, _VP]),
+    "gpcg_weighted_rows": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "gpcg_get_order": (C.c_int, [_VP, C.c_int32, _i32p]),
     "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
@@ -275,6 +278,36 @@ class Context:
         _check(self._lib.gpcg_solve_rhs(self._h, n_out, _ptr(outages), _ptr(rhs_cols), int(rhs_cols.stride(0)),
                                         float(tol), int(max_iter), _ptr(out["x"]), _ptr(out["iters"]),
                                         _ptr(out["status"]), _ptr(out["island"]), _ptr(out["resid"])))
+        return out
+
+    def overload_gradients(self, outages, P, F, kappa=20.0, tol=1e-12, max_iter=20000, *, grads=True):
+        """gpcg_overload_gradients: per-scenario overload loss and (with
+        grads) its gradients dL/dP [n_out, n_bus] and dL/dx [n_out, m].
+        Returns the dict of device tensors loss, grad_p, grad_x, iters,
+        status (iters and status: forward then adjoint, 2 n_out)."""
+        import torch
+
+        n_out = int(outages.shape[0])
+        dev = outages.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = {
+            "loss": torch.empty(n_out, **f64),
+            "grad_p": torch.empty((n_out, self.n_bus), **f64) if grads else None,
+            "grad_x": torch.empty((n_out, self.m), **f64) if grads else None,
+            "iters": torch.zeros(2 * n_out, dtype=torch.int32, device=dev),
+            "status": torch.zeros(2 * n_out, dtype=torch.int32, device=dev),
+        }
+        _check(self._lib.gpcg_overload_gradients(self._h, n_out, _ptr(outages), _ptr(P), _ptr(F), float(kappa),
+                                                 float(tol), int(max_iter), _ptr(out["loss"]), _ptr(out["grad_p"]),
+                                                 _ptr(out["grad_x"]), _ptr(out["iters"]), _ptr(out["status"])))
+        return out
+
+    def weighted_rows(self, a, w, out):
+        """gpcg_weighted_rows: out = w @ a for a row-major [n_rows, n_cols]."""
+        if a.dim() != 2 or a.stride(1) != 1:
+            raise ValueError("a must be a row-major 2-D tensor")
+        _check(self._lib.gpcg_weighted_rows(self._h, int(a.shape[0]), int(a.shape[1]), _ptr(a), int(a.stride(0)),
+                                            _ptr(w), _ptr(out)))
         return out
 
     def order(self, n_out) -> np.ndarray:

@@ -505,6 +505,8 @@ struct gpcg_context {
     DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
+    DevBuf<int32_t> inc_ptr, inc_br;  // branches at each bus
+    DevBuf<double> ov_theta, ov_flows, ov_g, ov_lambda;  // overload-gradient workspace
     int spmm_ch = 0, spmm_max_nnz = 0;  // chunk layout of A the stand-alone product reads
     DevBuf<double> c_val;
     DevBuf<int32_t> c_col, c_rp, c_pre;
@@ -927,6 +929,21 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->pre_bus.upload(h->topo.pre.data(), n_bus, st);
         h->isl_lo.upload(h->topo.lo.data(), m, st);
         h->isl_hi.upload(h->topo.hi.data(), m, st);
+        {  // branches incident to each bus, for gathers over a bus's branches
+            std::vector<int32_t> ptr(n_bus + 1, 0), br(2 * (size_t)m);
+            for (int e = 0; e < m; ++e) {
+                ++ptr[br_from[e] + 1];
+                ++ptr[br_to[e] + 1];
+            }
+            for (int k = 0; k < n_bus; ++k) ptr[k + 1] += ptr[k];
+            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+            for (int e = 0; e < m; ++e) {
+                br[fill[br_from[e]]++] = e;
+                br[fill[br_to[e]]++] = e;
+            }
+            h->inc_ptr.upload(ptr.data(), ptr.size(), st);
+            h->inc_br.upload(br.data(), br.size(), st);
+        }
         h->rho_b.alloc(nr);
         hip_check(hipStreamSynchronize(st), "setup upload");
         h->schedule_for(S);
@@ -1004,6 +1021,72 @@ int gpcg_solve_rhs(gpcg_t h, int32_t n_out, const int32_t *outages, const double
         if (!rhs_cols) fail(GPCG_E_ARG, "rhs_cols is NULL");
         run_solve(h, h->S, n_out, outages, nullptr, tol, max_iter, x_out, nullptr, iters_out, status_out, island_out,
                   resid_out, rhs_cols, ld);
+    });
+}
+
+int gpcg_overload_gradients(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs,
+                            const double *flow_limit, double kappa, double tol, int32_t max_iter, double *loss_out,
+                            double *grad_p_out, double *grad_x_out, int32_t *iters_out, int32_t *status_out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        if (h->kind != GPCG_KIND_BP) fail(GPCG_E_ARG, "the overload loss is defined on a B' context");
+        if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
+        if (!outages || !rhs || !flow_limit || !loss_out || !iters_out || !status_out)
+            fail(GPCG_E_ARG, "a required pointer is NULL");
+        if (!(kappa > 0.0) || !std::isfinite(kappa)) fail(GPCG_E_ARG, "kappa must be finite and > 0");
+        if (n_out == 0) return;
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        const size_t nb = (size_t)n_out * h->n_bus, nm = (size_t)n_out * h->m;
+        if (h->ov_theta.n < nb) {
+            h->ov_theta.alloc(nb);
+            h->ov_g.alloc(nb);
+            h->ov_lambda.alloc(nb);
+        }
+        if (h->ov_flows.n < nm) h->ov_flows.alloc(nm);
+        // forward: the scenario angles and flows (recomputed, nothing stored
+        // from an earlier call)
+        run_solve(h, h->S, n_out, outages, rhs, tol, max_iter, h->ov_theta.p, h->ov_flows.p, iters_out, status_out,
+                  nullptr, nullptr);
+        gpcg::OverloadParams o{};
+        o.n_bus = h->n_bus;
+        o.m = h->m;
+        o.n_out = n_out;
+        o.kappa = kappa;
+        o.br_from = h->br_from.p;
+        o.br_to = h->br_to.p;
+        o.br_x = h->br_x.p;
+        o.inc_ptr = h->inc_ptr.p;
+        o.inc_br = h->inc_br.p;
+        o.pre_bus = h->pre_bus.p;
+        o.isl_lo = h->isl_lo.p;
+        o.isl_hi = h->isl_hi.p;
+        o.outages = outages;
+        o.P = rhs;
+        o.F = flow_limit;
+        o.theta = h->ov_theta.p;
+        o.flows = h->ov_flows.p;
+        o.lambda = h->ov_lambda.p;
+        o.g = h->ov_g.p;
+        o.loss = loss_out;
+        o.grad_p = grad_p_out;
+        o.grad_x = grad_x_out;
+        hip_check(gpcg::launch_overload_seed(o, h->stream), "overload seed");
+        if (!grad_p_out && !grad_x_out) return;
+        // adjoint: A_c[M,M] lambda = g_M with the same preconditioner
+        run_solve(h, h->S, n_out, outages, nullptr, tol, max_iter, h->ov_lambda.p, nullptr, iters_out + n_out,
+                  status_out + n_out, nullptr, nullptr, h->ov_g.p, h->n_bus);
+        hip_check(gpcg::launch_overload_grads(o, h->stream), "overload gradients");
+    });
+}
+
+int gpcg_weighted_rows(gpcg_t h, int32_t n_rows, int32_t n_cols, const double *a, int32_t lda, const double *w,
+                       double *out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        if (n_rows < 0 || n_cols < 0 || lda < n_cols) fail(GPCG_E_ARG, "bad sizes");
+        if ((n_rows && n_cols && (!a || !w)) || (n_cols && !out)) fail(GPCG_E_ARG, "a required pointer is NULL");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        hip_check(gpcg::launch_weighted_rows(n_rows, n_cols, a, lda, w, out, h->stream), "weighted rows");
     });
 }
 

@@ -123,6 +123,28 @@ struct SpmmParams {
     double *q, *pq;
 };
 
+// Branch-overload loss L = sum_e softplus(kappa (|f_e| / F_e - 1)) of every
+// scenario and its gradients by the adjoint method: with s_e = dL/df_e and
+// g = dL/dtheta = D^T s (D: flows as a map of the angles), the adjoint
+// lambda solves A_c[M,M] lambda_M = g_M; then
+//   dL/dx_e = -s_e f_e / x_e + (lambda_f - lambda_t)(theta_f - theta_t) / x_e^2
+// (0 for the outaged branch), and dL/dP = (dP'/dP)^T lambda through the
+// re-dispatch.  Scenario-major arrays: theta, lambda, g [n_out * n_bus],
+// flows and dL/dx [n_out * m].
+struct OverloadParams {
+    int n_bus, m, n_out;
+    double kappa;
+    const int32_t *br_from, *br_to;
+    const double *br_x;
+    const int32_t *inc_ptr, *inc_br;  // branches incident to each bus (CSR over buses)
+    const int32_t *pre_bus;
+    const int32_t *isl_lo, *isl_hi;
+    const int32_t *outages;
+    const double *P, *F;  // injections [n_bus], flow limits [m]
+    const double *theta, *flows, *lambda;
+    double *g, *loss, *grad_p, *grad_x;
+};
+
 // Launchers (launch_pcg in gpcg_tile.hip, the rest in gpcg_kernels.hip).  They
 // return hipSuccess or the launch error.
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st);
@@ -142,6 +164,13 @@ bool spmm_chunk_fits(int S, int ch, int max_nnz);
 hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int ch, int nseg, int max_nnz, double *partial,
                                hipStream_t st);
 hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st);
+// seed g = dL/dtheta and the per-scenario loss (after the forward solve)
+hipError_t launch_overload_seed(const OverloadParams &prm, hipStream_t st);
+// dL/dP and dL/dx from theta, flows and lambda (after the adjoint solve)
+hipError_t launch_overload_grads(const OverloadParams &prm, hipStream_t st);
+// out[j] = sum_r w[r] a[r * lda + j]
+hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda, const double *w, double *out,
+                                hipStream_t st);
 
 // Order scenarios by expected PCG work so that a tile's columns stop at
 // about the same iteration: non-islanding outages first, then islanding

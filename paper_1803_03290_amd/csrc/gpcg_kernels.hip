@@ -351,6 +351,137 @@ __global__ void spmm_pq_reduce_kernel(int ncols, int chunks, const double *parti
     pq[col] = a;
 }
 
+// ---------------------------------------------------------------------------
+// Branch-overload loss and its adjoint gradients (see OverloadParams).
+
+__device__ __forceinline__ double softplus(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+
+__device__ __forceinline__ double sigmoid(double z) {
+    const double e = exp(-fabs(z));
+    return z >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+}
+
+// s_e = dL/df_e = sigma(z) kappa sign(f_e) / F_e, z = kappa (|f_e| / F_e - 1);
+// 0 where the flow is exactly 0 (the outaged branch, island branches)
+__device__ __forceinline__ double flow_seed(const OverloadParams &p, const double *f, int e) {
+    const double fe = f[e], Fe = p.F[e];
+    if (fe == 0.0) return 0.0;
+    const double z = p.kappa * (fabs(fe) / Fe - 1.0);
+    return sigmoid(z) * p.kappa * (fe > 0.0 ? 1.0 : -1.0) / Fe;
+}
+
+// g_k = sum over branches e at bus k of +-s_e / x_e (+ at the from end)
+__global__ void overload_seed_kernel(OverloadParams p) {
+    const int s = blockIdx.x;
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    if (k >= p.n_bus) return;
+    const double *f = p.flows + (size_t)s * p.m;
+    double g = 0.0;
+    for (int t = p.inc_ptr[k]; t < p.inc_ptr[k + 1]; ++t) {
+        const int e = p.inc_br[t];
+        const double v = flow_seed(p, f, e) / p.br_x[e];
+        g += (p.br_from[e] == k) ? v : -v;
+    }
+    p.g[(size_t)s * p.n_bus + k] = g;
+}
+
+// per-scenario loss, summed over the branches in a fixed order
+__global__ void __launch_bounds__(256) overload_loss_kernel(OverloadParams p) {
+    __shared__ double sh[256];
+    const int s = blockIdx.x;
+    const double *f = p.flows + (size_t)s * p.m;
+    double L = 0.0;
+    for (int e = threadIdx.x; e < p.m; e += blockDim.x) L += softplus(p.kappa * (fabs(f[e]) / p.F[e] - 1.0));
+    sh[threadIdx.x] = L;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.loss[s] = sh[0];
+}
+
+__global__ void overload_grad_x_kernel(OverloadParams p) {
+    const int s = blockIdx.x;
+    const int e = blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= p.m) return;
+    const int c = p.outages[s];
+    double d = 0.0;
+    if (e != c && c >= -1 && c < p.m) {
+        const double *th = p.theta + (size_t)s * p.n_bus;
+        const double *la = p.lambda + (size_t)s * p.n_bus;
+        const double *f = p.flows + (size_t)s * p.m;
+        const int a = p.br_from[e], b = p.br_to[e];
+        const double x = p.br_x[e];
+        d = -flow_seed(p, f, e) * f[e] / x + (la[a] - la[b]) * (th[a] - th[b]) / (x * x);
+    }
+    p.grad_x[(size_t)s * p.m + e] = d;
+}
+
+// dL/dP_k through the re-dispatch of Section IV.C: with islanded power
+// dP = sum_I P, main generators G (non-slack, P > 0), S = sum_G P and
+// T = sum_G lambda P:  lambda_k on M \ G;  lambda_k (1 + dP/S) - T dP / S^2
+// on G;  T / S on I.  Without generators (or without an island) it is
+// lambda on M and 0 on I.  The slack's injection is not an input.
+__global__ void __launch_bounds__(256) overload_grad_p_kernel(OverloadParams p) {
+    __shared__ double sh[3][256];
+    const int s = blockIdx.x;
+    const int c = p.outages[s];
+    const bool bad = c < -1 || c >= p.m;
+    int lo = 0, hi = 0;
+    if (!bad && c >= 0) {
+        lo = p.isl_lo[c];
+        hi = p.isl_hi[c];
+    }
+    const double *la = p.lambda + (size_t)s * p.n_bus;
+    double dP = 0.0, S = 0.0, T = 0.0;
+    for (int k = 1 + threadIdx.x; k < p.n_bus; k += blockDim.x) {
+        const double Pk = p.P[k];
+        if (in_interval(p.pre_bus[k], lo, hi)) {
+            dP += Pk;
+        } else if (Pk > 0.0) {
+            S += Pk;
+            T += la[k] * Pk;
+        }
+    }
+    sh[0][threadIdx.x] = dP;
+    sh[1][threadIdx.x] = S;
+    sh[2][threadIdx.x] = T;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int v = 0; v < 3; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    dP = sh[0][0];
+    S = sh[1][0];
+    T = sh[2][0];
+    const bool redis = hi > lo && S > 0.0;
+    for (int k = threadIdx.x; k < p.n_bus; k += blockDim.x) {
+        double d = 0.0;
+        if (k > 0 && !bad) {
+            const double Pk = p.P[k];
+            if (in_interval(p.pre_bus[k], lo, hi))
+                d = redis ? T / S : 0.0;
+            else if (redis && Pk > 0.0)
+                d = la[k] * (1.0 + dP / S) - T * dP / (S * S);
+            else
+                d = la[k];
+        }
+        p.grad_p[(size_t)s * p.n_bus + k] = d;
+    }
+}
+
+// out[j] = sum_r w[r] a[r * lda + j], rows summed in order (deterministic)
+__global__ void weighted_rows_kernel(int n_rows, int n_cols, const double *a, int lda, const double *w,
+                                     double *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_cols) return;
+    double acc = 0.0;
+    for (int r = 0; r < n_rows; ++r) acc += w[r] * a[(size_t)r * lda + j];
+    out[j] = acc;
+}
+
 // sort key of a scenario: islanding flag, then the base flow on the branch
 __global__ void order_keys_kernel(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
                                   const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi,
@@ -422,6 +553,31 @@ hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta,
 
 hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st) {
     hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, st, n, v, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_overload_seed(const OverloadParams &prm, hipStream_t st) {
+    if (prm.n_out <= 0) return hipSuccess;
+    const int tb = 256;
+    hipLaunchKernelGGL(overload_seed_kernel, dim3(prm.n_out, (prm.n_bus + tb - 1) / tb), dim3(tb), 0, st, prm);
+    hipLaunchKernelGGL(overload_loss_kernel, dim3(prm.n_out), dim3(256), 0, st, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_overload_grads(const OverloadParams &prm, hipStream_t st) {
+    if (prm.n_out <= 0) return hipSuccess;
+    const int tb = 256;
+    if (prm.grad_x)
+        hipLaunchKernelGGL(overload_grad_x_kernel, dim3(prm.n_out, (prm.m + tb - 1) / tb), dim3(tb), 0, st, prm);
+    if (prm.grad_p) hipLaunchKernelGGL(overload_grad_p_kernel, dim3(prm.n_out), dim3(256), 0, st, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda, const double *w, double *out,
+                                hipStream_t st) {
+    if (n_cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(weighted_rows_kernel, dim3((n_cols + 255) / 256), dim3(256), 0, st, n_rows, n_cols, a, lda, w,
+                       out);
     return hipGetLastError();
 }
 

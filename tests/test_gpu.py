@@ -329,3 +329,111 @@ def test_solve_rhs_edges(gp, grids):
         assert np.abs(x[s] - d["theta"]).max() <= ANGLE_TOL
     with pytest.raises(gp.GpcgError):
         ctx.solve_rhs(torch.tensor(outs, device="cuda"), torch.tensor(B[:, :-1].copy(), device="cuda"))
+
+
+# -------------------------------------- overload loss and adjoint gradients
+
+
+def _overload(gp, ctx, g, outs, F, tol=1e-12, grads=True):
+    o = torch.tensor(np.asarray(outs, np.int32), device="cuda")
+    res = ctx.overload_gradients(o, torch.tensor(g.P, device="cuda"), torch.tensor(F, device="cuda"), 20.0, tol=tol,
+                                 grads=grads)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in res.items()}
+
+
+def test_overload_gradients_grid200_all_outages(gp, grids):
+    """Loss, dL/dP and dL/dx of every outage (and the intact grid) against
+    the oracle's dense-Jacobian gradients: relative error <= 1e-6 of each
+    gradient's largest entry; statuses of both solves."""
+    from oracle import adjoint
+
+    g = grids["grid200"]
+    F = adjoint.flow_limits(g)
+    ctx = _ctx(gp, g, block=16)
+    outs = np.arange(-1, g.m)
+    res = _overload(gp, ctx, g, outs, F)
+    n = len(outs)
+    for s, c in enumerate(outs):
+        L, dP, dx = adjoint.gradients_dense(g, int(c), g.P, g.x, F)
+        assert res["loss"][s] == pytest.approx(L, rel=1e-9, abs=1e-12), c
+        assert np.abs(res["grad_p"][s] - dP).max() <= 1e-6 * max(np.abs(dP).max(), 1e-12), c
+        assert np.abs(res["grad_x"][s] - dx).max() <= 1e-6 * max(np.abs(dx).max(), 1e-12), c
+        isl = oracle.island_of(g, int(c)).any()
+        assert res["status"][n + s] == (gp.CONVERGED_ISLANDED if isl else gp.CONVERGED), c
+        assert res["status"][s] in (gp.CONVERGED, gp.CONVERGED_ISLANDED, gp.ISLANDED_NO_GEN), c
+
+
+def test_overload_autograd_function(gp, grids):
+    """torch.autograd through OverloadLoss: the gradients of sum_j w_j L_j
+    with seeded weights against the oracle's weighted dense gradients; the
+    loss-only forward matches the gradient call's loss."""
+    from oracle import adjoint
+
+    g = grids["grid200"]
+    F = adjoint.flow_limits(g)
+    ctx = _ctx(gp, g, block=16)
+    outs = np.arange(0, g.m, 3)
+    o = torch.tensor(outs.astype(np.int32), device="cuda")
+    P = torch.tensor(g.P, device="cuda", requires_grad=True)
+    x = torch.tensor(g.x, device="cuda", requires_grad=True)
+    Ft = torch.tensor(F, device="cuda")
+    loss = gp.overload_loss(P, x, ctx, o, Ft)
+    w = torch.tensor(np.random.default_rng(9).uniform(0.5, 1.5, len(outs)), device="cuda")
+    (loss * w).sum().backward()
+    torch.cuda.synchronize()
+    gP = np.zeros(g.n)
+    gx = np.zeros(g.m)
+    wh = w.cpu().numpy()
+    Ls = []
+    for k, c in enumerate(outs):
+        L, dP, dx = adjoint.gradients_dense(g, int(c), g.P, g.x, F)
+        gP += wh[k] * dP
+        gx += wh[k] * dx
+        Ls.append(L)
+    np.testing.assert_allclose(loss.detach().cpu().numpy(), Ls, rtol=1e-9)
+    assert np.abs(P.grad.cpu().numpy() - gP).max() <= 1e-6 * np.abs(gP).max()
+    assert np.abs(x.grad.cpu().numpy() - gx).max() <= 1e-6 * np.abs(gx).max()
+
+
+def test_overload_gradients_grid10k_sampled_fd(gp, grids):
+    """The differentiation workload at full size: every outage of the
+    10,000-bus grid in one call at block 16; for 3 seeded outages, 9 seeded
+    entries of dL/dP and 8 of dL/dx (51 in all) against central differences
+    of the oracle's refined direct loss, to 1e-6 of the gradient's largest
+    entry.  The step is h = 1e-6 first.  Angles reach thousands of radians on
+    this grid, so even the refined loss carries rounding noise of a few 1e-9,
+    which a step of 1e-6 amplifies past the bar on some entries; those are
+    checked with the Richardson extrapolation (4 D(h/2) - D(h)) / 3 of
+    central differences at h = 1e-4, which removes the h^2 term while the
+    noise stays about 1e-4 times smaller than at h = 1e-6."""
+    from oracle import adjoint
+
+    g = grids["grid10k"]
+    F = adjoint.flow_limits(g)
+    ctx = _ctx(gp, g, block=16)
+    outs = np.arange(g.m)
+    res = _overload(gp, ctx, g, outs, F)
+    assert np.all(res["status"][g.m:] <= gp.CONVERGED_ISLANDED)
+
+    def fd(fun, v, j, h):
+        vp, vm = v.copy(), v.copy()
+        vp[j] += h
+        vm[j] -= h
+        return (fun(vp) - fun(vm)) / (2 * h)
+
+    def check(fun, v, j, grad, scale):
+        d1 = fd(fun, v, j, 1e-6)
+        if abs(d1 - grad) <= 1e-6 * scale:
+            return
+        d2 = (4.0 * fd(fun, v, j, 5e-5) - fd(fun, v, j, 1e-4)) / 3.0
+        assert abs(d2 - grad) <= 1e-6 * scale, (j, d1, d2, grad)
+
+    rng = np.random.default_rng(17)
+    for c in rng.choice(g.m, 3, replace=False):
+        gp_row, gx_row = res["grad_p"][c], res["grad_x"][c]
+        sp_, sx_ = max(np.abs(gp_row).max(), 1.0), max(np.abs(gx_row).max(), 1.0)
+        for j in rng.choice(np.arange(1, g.n), 9, replace=False):
+            check(lambda v: adjoint.scenario_loss(g, int(c), v, g.x, F), g.P, j, gp_row[j], sp_)
+        for e in rng.choice(g.m, 8, replace=False):
+            check(lambda v: adjoint.scenario_loss(g, int(c), g.P, v, F), g.x, e, gx_row[e], sx_)
