@@ -153,15 +153,13 @@ def cpu_baseline(grid, seconds: float = 12.0):
 
 
 # ------------------------------------------------------ stand-alone SpMM
-def spmm_measure(gp, torch, workload: str, S: int = 64, reps: int = 20):
+def spmm_measure(gp, torch, grid, S: int = 64, reps: int = 20):
     """The outage-corrected product q = A_c p over every outage column of a
     grid in one launch (p ~ N(0, 1), seed 0, columns padded to a multiple
     of S), timed with HIP events; bytes are the product's algorithmic bytes
     12 nnz + 4 (n_r + 1) + 16 n_r s + 16 s for s columns."""
-    import gridgen
     import numpy as np
 
-    grid = gridgen.make_grid(workload)
     ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=S)
     info = ctx.info()
     nr = info["n_r"]
@@ -193,6 +191,41 @@ def spmm_measure(gp, torch, workload: str, S: int = 64, reps: int = 20):
             "median_ms": ms, "algorithmic_bytes": nbytes, "block": S}
 
 
+def adjoint_measure(gp, torch, grid, S: int = 16, reps: int = 2, tol: float = 1e-12):
+    """The differentiation workload: the overload loss of every outage and
+    its gradients in P (n) and x (m), one forward and one adjoint batched
+    PCG per scenario, timed with HIP events on the context's stream.  Flow
+    limits F = 1.2 |base flow| + 0.1 come from the library's own base-case
+    solve (input preparation, outside the timed region)."""
+    import numpy as np
+
+    ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=S)
+    dev = torch.device("cuda", 0)
+    P = torch.tensor(grid.P, dtype=torch.float64, device=dev)
+    base = ctx.solve(torch.tensor([-1], dtype=torch.int32, device=dev), P, tol=tol)
+    F = 1.2 * base["flows"][0].abs() + 0.1
+    outs = torch.arange(grid.m, dtype=torch.int32, device=dev)
+    res = ctx.overload_gradients(outs, P, F, 20.0, tol=tol)
+    torch.cuda.synchronize()
+    stream = ctx.stream
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        res = ctx.overload_gradients(outs, P, F, 20.0, tol=tol)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    it = res["iters"].cpu().numpy()
+    st = res["status"].cpu().numpy()
+    return {"workload": f"{grid.name}: overload loss + dL/dP ({grid.n}) + dL/dx ({grid.m}) of all {grid.m} "
+                        f"outages, forward + adjoint batched PCG (base ILU(0)), tol {tol:g}",
+            "value": grid.m / (ms * 1e-3), "unit": "scenarios/s", "ms": ms, "block": S,
+            "forward_iters_mean": float(it[:grid.m].mean()), "adjoint_iters_mean": float(it[grid.m:].mean()),
+            "all_converged": bool(np.all(st <= 5))}
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -213,6 +246,10 @@ def main():
     ap.add_argument("--no-spmm", action="store_true")
     ap.add_argument("--spmm-block", type=int, default=32)
     ap.add_argument("--spmm-only", action="store_true", help="only the stand-alone product measurement")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-workload", default="grid10k", help="grid of the overload-gradient measurement")
+    ap.add_argument("--adjoint-block", type=int, default=16)
+    ap.add_argument("--adjoint-only", action="store_true", help="only the overload-gradient measurement")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -254,8 +291,19 @@ def main():
     gp.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    aux_grids = {}
+
+    def aux_grid(name):
+        if name not in aux_grids:
+            aux_grids[name] = grid if name == grid.name else gridgen.make_grid(name)
+        return aux_grids[name]
+
     if args.spmm_only:
-        print(json.dumps(spmm_measure(gp, torch, args.spmm_workload, args.spmm_block)), flush=True)
+        print(json.dumps(spmm_measure(gp, torch, aux_grid(args.spmm_workload), args.spmm_block)), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps(adjoint_measure(gp, torch, aux_grid(args.adjoint_workload), args.adjoint_block)),
+              flush=True)
         return
     t0 = time.perf_counter()
     block = args.block or auto_block(grid.m)
@@ -325,7 +373,9 @@ def main():
                  "ms": p_ms, "max_abs_diff_vs_batched_rad": same,
                  "note": "seeded sample, one scenario per launch, lanes spread over rows (S=1)"}
 
-    spmm = None if args.no_spmm else spmm_measure(gp, torch, args.spmm_workload, args.spmm_block)
+    spmm = None if args.no_spmm else spmm_measure(gp, torch, aux_grid(args.spmm_workload), args.spmm_block)
+    adj = None if args.no_adjoint else adjoint_measure(gp, torch, aux_grid(args.adjoint_workload),
+                                                       args.adjoint_block)
 
     value = m / (ms_step * 1e-3)
     st_counts = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
@@ -357,6 +407,7 @@ def main():
             "avg_launch_ms": pcg_ms, "kernel_digest": kernel_digest(),
         },
         "spmm": spmm,
+        "adjoint": adj,
         "cpu_baseline": cpu,
         "verify": {
             "status_counts": st_counts,

@@ -279,6 +279,38 @@ int gpcg_weighted_rows(gpcg_t h, int32_t n_rows, int32_t n_cols, const double *a
                        double *out);
 
 /*
+ * Fast-decoupled AC power flow of every outage (Section II, eqs. (1)-(5)):
+ * n_outer iterations, each a P-theta half (B'_c dtheta = dP / V, then
+ * theta += dtheta) and a Q-V half with the updated angles (B''_c dV = dQ / V,
+ * then V += dV), every half a batched PCG solve with one right-hand side
+ * per scenario and the base-case ILU(0) of its matrix.  The network is
+ * lossless and tap-free (branch reactances only) with bus shunts b_sh; the
+ * injections it takes are
+ *   P_k = sum_j V_k V_j sin(theta_k - theta_j) / x_kj,
+ *   Q_k = V_k^2 (sum_j 1 / x_kj + b_sh,k) - sum_j V_k V_j cos(theta_k - theta_j) / x_kj,
+ * over the branches in service.  The slack (bus 0) holds theta = 0, V = 1;
+ * every other bus is a load bus with the specified P and Q.  Islanded buses
+ * are left out of every equation and reported as theta = 0, V = 1; the
+ * islanded active power is re-dispatched as in the DC screening
+ * (Section IV.C).
+ *   bp, bpp      a B' context and a B'' context (with the shunts on its
+ *                diagonal) of the same grid on the same device and stream.
+ *   P, Q         device f64[n_bus] specified injections (slack ignored).
+ *   theta0, V0   device f64[n_bus], the state every scenario starts from
+ *                (a flat start, or the base case's state).
+ *   theta_out, V_out  device f64[n_out * n_bus] (scenario-major).
+ *   iters_out    device int32[n_out]: PCG iterations over all halves.
+ *   status_out   device int32[n_out]: the first failure of any half, else
+ *                GPCG_CONVERGED(_ISLANDED) or GPCG_ISLANDED_NO_GEN.
+ * The power-flow iteration itself is not checked for convergence: the
+ * caller picks n_outer.  Errors: GPCG_E_ARG for NULL pointers, swapped or
+ * mismatched contexts, n_outer < 1.  Asynchronous on the shared stream.
+ */
+int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, const double *P, const double *Q,
+              const double *theta0, const double *V0, int32_t n_outer, double tol, int32_t max_iter,
+              double *theta_out, double *V_out, int32_t *iters_out, int32_t *status_out);
+
+/*
  * The same computation with the plain per-scenario PCG: one scenario at a
  * time (S = 1), each as its own launch in the context's stream, with the
  * wavefront's 64 lanes spread over rows instead of scenarios.  Same

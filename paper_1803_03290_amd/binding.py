@@ -66,6 +66,8 @@ SIGNATURES = {
     "gpcg_overload_gradients": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double, C.c_double, C.c_int32, _VP,
                                           _VP, _VP, _VP, _VP]),
     "gpcg_weighted_rows": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
+    "gpcg_fdpf": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP,
+                            _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "gpcg_get_order": (C.c_int, [_VP, C.c_int32, _i32p]),
     "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
@@ -308,6 +310,26 @@ class Context:
             raise ValueError("a must be a row-major 2-D tensor")
         _check(self._lib.gpcg_weighted_rows(self._h, int(a.shape[0]), int(a.shape[1]), _ptr(a), int(a.stride(0)),
                                             _ptr(w), _ptr(out)))
+        return out
+
+    def fdpf(self, bpp, outages, P, Q, theta0, V0, n_outer=3, tol=1e-12, max_iter=20000):
+        """gpcg_fdpf with this (B') context and the B'' context ``bpp``:
+        n_outer fast-decoupled iterations of every outage from (theta0, V0).
+        Returns the dict of device tensors theta, V [n_out, n_bus], iters,
+        status."""
+        import torch
+
+        n_out = int(outages.shape[0])
+        dev = outages.device
+        out = {
+            "theta": torch.empty((n_out, self.n_bus), dtype=torch.float64, device=dev),
+            "V": torch.empty((n_out, self.n_bus), dtype=torch.float64, device=dev),
+            "iters": torch.empty(n_out, dtype=torch.int32, device=dev),
+            "status": torch.empty(n_out, dtype=torch.int32, device=dev),
+        }
+        _check(self._lib.gpcg_fdpf(self._h, bpp._h, n_out, _ptr(outages), _ptr(P), _ptr(Q), _ptr(theta0), _ptr(V0),
+                                   int(n_outer), float(tol), int(max_iter), _ptr(out["theta"]), _ptr(out["V"]),
+                                   _ptr(out["iters"]), _ptr(out["status"])))
         return out
 
     def order(self, n_out) -> np.ndarray:

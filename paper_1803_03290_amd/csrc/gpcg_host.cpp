@@ -507,6 +507,9 @@ struct gpcg_context {
     DevBuf<double> ws, gfac, partial;
     DevBuf<int32_t> inc_ptr, inc_br;  // branches at each bus
     DevBuf<double> ov_theta, ov_flows, ov_g, ov_lambda;  // overload-gradient workspace
+    DevBuf<double> diag_bus;                             // diagonal of A by bus (slack 0), built on first use
+    DevBuf<double> fd_rhs, fd_dx, fd_gfac;               // power-flow workspace
+    DevBuf<int32_t> fd_nogen, fd_it, fd_st;
     int spmm_ch = 0, spmm_max_nnz = 0;  // chunk layout of A the stand-alone product reads
     DevBuf<double> c_val;
     DevBuf<int32_t> c_col, c_rp, c_pre;
@@ -1087,6 +1090,83 @@ int gpcg_weighted_rows(gpcg_t h, int32_t n_rows, int32_t n_cols, const double *a
         if ((n_rows && n_cols && (!a || !w)) || (n_cols && !out)) fail(GPCG_E_ARG, "a required pointer is NULL");
         hip_check(hipSetDevice(h->device), "hipSetDevice");
         hip_check(gpcg::launch_weighted_rows(n_rows, n_cols, a, lda, w, out, h->stream), "weighted rows");
+    });
+}
+
+int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, const double *P, const double *Q,
+              const double *theta0, const double *V0, int32_t n_outer, double tol, int32_t max_iter,
+              double *theta_out, double *V_out, int32_t *iters_out, int32_t *status_out) {
+    return guarded([&] {
+        if (!bp || !bpp) fail(GPCG_E_ARG, "context is NULL");
+        if (bp->kind != GPCG_KIND_BP || bpp->kind != GPCG_KIND_BPP)
+            fail(GPCG_E_ARG, "the first context must be B' and the second B''");
+        if (bp->n_bus != bpp->n_bus || bp->m != bpp->m) fail(GPCG_E_ARG, "the two contexts hold different grids");
+        if (bp->stream != bpp->stream || bp->device != bpp->device)
+            fail(GPCG_E_ARG, "the two contexts must share a device and a stream");
+        if (n_out < 0 || n_outer < 1) fail(GPCG_E_ARG, "n_out < 0 or n_outer < 1");
+        if (n_out == 0) return;
+        if (!outages || !P || !Q || !theta0 || !V0 || !theta_out || !V_out || !iters_out || !status_out)
+            fail(GPCG_E_ARG, "a required pointer is NULL");
+        hip_check(hipSetDevice(bp->device), "hipSetDevice");
+        if (!bpp->diag_bus.p) {
+            std::vector<double> d(bpp->n_bus, 0.0);
+            for (int i = 0; i < bpp->n_r; ++i)
+                for (int e = bpp->hA.rowptr[i]; e < bpp->hA.rowptr[i + 1]; ++e)
+                    if (bpp->hA.col[e] == i) d[i + 1] = bpp->hA.val[e];
+            bpp->diag_bus.upload(d.data(), d.size(), bpp->stream);
+            hip_check(hipStreamSynchronize(bpp->stream), "diagonal upload");
+        }
+        const size_t nb = (size_t)n_out * bp->n_bus;
+        if (bp->fd_rhs.n < nb) {
+            bp->fd_rhs.alloc(nb);
+            bp->fd_dx.alloc(nb);
+        }
+        if (bp->fd_gfac.n < (size_t)n_out) {
+            bp->fd_gfac.alloc(n_out);
+            bp->fd_nogen.alloc(n_out);
+            bp->fd_it.alloc(n_out);
+            bp->fd_st.alloc(n_out);
+        }
+        gpcg::FdpfParams f{};
+        f.n_bus = bp->n_bus;
+        f.m = bp->m;
+        f.n_out = n_out;
+        f.br_from = bp->br_from.p;
+        f.br_to = bp->br_to.p;
+        f.br_b = bp->br_b.p;
+        f.inc_ptr = bp->inc_ptr.p;
+        f.inc_br = bp->inc_br.p;
+        f.pre_bus = bp->pre_bus.p;
+        f.isl_lo = bp->isl_lo.p;
+        f.isl_hi = bp->isl_hi.p;
+        f.outages = outages;
+        f.P = P;
+        f.Q = Q;
+        f.diag_bpp = bpp->diag_bus.p;
+        f.theta0 = theta0;
+        f.V0 = V0;
+        f.theta = theta_out;
+        f.V = V_out;
+        f.rhs = bp->fd_rhs.p;
+        f.dx = bp->fd_dx.p;
+        f.gfac = bp->fd_gfac.p;
+        f.nogen = bp->fd_nogen.p;
+        f.iters = iters_out;
+        f.status = status_out;
+        f.it_step = bp->fd_it.p;
+        f.st_step = bp->fd_st.p;
+        hipStream_t st = bp->stream;
+        hip_check(gpcg::launch_fdpf(f, 0, 0, st), "fdpf start");
+        for (int k = 0; k < n_outer; ++k) {
+            for (int half = 0; half < 2; ++half) {
+                gpcg_context *h = half ? bpp : bp;
+                hip_check(gpcg::launch_fdpf(f, 1, half, st), "fdpf mismatch");
+                run_solve(h, h->S, n_out, outages, nullptr, tol, max_iter, bp->fd_dx.p, nullptr, bp->fd_it.p,
+                          bp->fd_st.p, nullptr, nullptr, bp->fd_rhs.p, bp->n_bus);
+                hip_check(gpcg::launch_fdpf(f, 2, half, st), "fdpf update");
+            }
+        }
+        hip_check(gpcg::launch_fdpf(f, 3, 0, st), "fdpf finish");
     });
 }
 

@@ -145,6 +145,29 @@ struct OverloadParams {
     double *g, *loss, *grad_p, *grad_x;
 };
 
+// Fast-decoupled power flow of every outage (Section II, eqs. (1)-(5)) on a
+// lossless, tap-free network with bus shunts: per outer iteration a P-theta
+// half (B'_c dtheta = dP / V) and a Q-V half (B''_c dV = dQ / V), each a
+// batched solve with a right-hand side per scenario.  State theta, V and the
+// right-hand sides are scenario-major [n_out * n_bus].
+struct FdpfParams {
+    int n_bus, m, n_out;
+    const int32_t *br_from, *br_to;
+    const double *br_b;
+    const int32_t *inc_ptr, *inc_br;
+    const int32_t *pre_bus, *isl_lo, *isl_hi;
+    const int32_t *outages;
+    const double *P, *Q;     // specified injections [n_bus]
+    const double *diag_bpp;  // B'' diagonal by bus: sum of 1/x at the bus + its shunt
+    const double *theta0, *V0;
+    double *theta, *V, *rhs;
+    const double *dx;
+    double *gfac;                     // per scenario: re-dispatch factor
+    int32_t *nogen;                   // per scenario: islanded with no main generator
+    int32_t *iters, *status;          // accumulated over the half-iterations
+    const int32_t *it_step, *st_step;  // the last half-iteration's solve
+};
+
 // Launchers (launch_pcg in gpcg_tile.hip, the rest in gpcg_kernels.hip).  They
 // return hipSuccess or the launch error.
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st);
@@ -168,6 +191,10 @@ hipError_t launch_sumsq(int n, const double *v, double *out, hipStream_t st);
 hipError_t launch_overload_seed(const OverloadParams &prm, hipStream_t st);
 // dL/dP and dL/dx from theta, flows and lambda (after the adjoint solve)
 hipError_t launch_overload_grads(const OverloadParams &prm, hipStream_t st);
+// fast-decoupled power flow: 0 start from (theta0, V0) and re-dispatch;
+// 1 mismatch of half h into rhs; 2 state += dx for half h and accumulate
+// the solve's iterations and status; 3 islands to theta = 0, V = 1
+hipError_t launch_fdpf(const FdpfParams &prm, int phase, int half, hipStream_t st);
 // out[j] = sum_r w[r] a[r * lda + j]
 hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda, const double *w, double *out,
                                 hipStream_t st);

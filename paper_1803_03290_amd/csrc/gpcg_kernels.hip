@@ -472,6 +472,131 @@ __global__ void __launch_bounds__(256) overload_grad_p_kernel(OverloadParams p) 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fast-decoupled power flow (see FdpfParams).
+
+__device__ __forceinline__ bool fdpf_island(const FdpfParams &p, int c, int k) {
+    return c >= 0 && in_interval(p.pre_bus[k], p.isl_lo[c], p.isl_hi[c]);
+}
+
+__global__ void fdpf_start_kernel(FdpfParams p) {
+    const int s = blockIdx.x;
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    if (k >= p.n_bus) return;
+    const size_t o = (size_t)s * p.n_bus + k;
+    p.theta[o] = k ? p.theta0[k] : 0.0;
+    p.V[o] = k ? p.V0[k] : 1.0;
+}
+
+// re-dispatch factor of each scenario (Section IV.C) and its no-generator
+// flag; clears the accumulated iterations and status
+__global__ void __launch_bounds__(256) fdpf_redispatch_kernel(FdpfParams p) {
+    __shared__ double sh[2][256];
+    const int s = blockIdx.x;
+    const int c = p.outages[s];
+    const bool ok = c >= 0 && c < p.m;
+    double dP = 0.0, S = 0.0;
+    for (int k = 1 + threadIdx.x; k < p.n_bus; k += blockDim.x) {
+        const double Pk = p.P[k];
+        if (ok && fdpf_island(p, c, k))
+            dP += Pk;
+        else if (Pk > 0.0)
+            S += Pk;
+    }
+    sh[0][threadIdx.x] = dP;
+    sh[1][threadIdx.x] = S;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool island = ok && p.isl_hi[c] > p.isl_lo[c];
+        p.gfac[s] = (island && sh[1][0] > 0.0) ? sh[0][0] / sh[1][0] : 0.0;
+        p.nogen[s] = (island && !(sh[1][0] > 0.0)) ? 1 : 0;
+        p.iters[s] = 0;
+        p.status[s] = (c < -1 || c >= p.m) ? kBadOutage : kConverged;
+    }
+}
+
+// rhs = (specified - taken) / V at every main-system load bus, 0 elsewhere
+//   half 0: P_k = sum_e V_k V_j b_e sin(theta_k - theta_j)
+//   half 1: Q_k = V_k^2 (sum_e b_e + b_sh,k) - sum_e V_k V_j b_e cos(theta_k - theta_j)
+// over the branches e = (k, j) in service (the outaged one is skipped).
+__global__ void fdpf_mismatch_kernel(FdpfParams p, int half) {
+    const int s = blockIdx.x;
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    if (k >= p.n_bus) return;
+    const int c = p.outages[s];
+    const size_t o = (size_t)s * p.n_bus + k;
+    if (k == 0 || c < -1 || c >= p.m || fdpf_island(p, c, k)) {
+        p.rhs[o] = 0.0;
+        return;
+    }
+    const double *th = p.theta + (size_t)s * p.n_bus;
+    const double *V = p.V + (size_t)s * p.n_bus;
+    const double tk = th[k], vk = V[k];
+    double acc = 0.0, cut = 0.0;
+    for (int t = p.inc_ptr[k]; t < p.inc_ptr[k + 1]; ++t) {
+        const int e = p.inc_br[t];
+        if (e == c) {
+            cut += p.br_b[e];
+            continue;
+        }
+        const int j = (p.br_from[e] == k) ? p.br_to[e] : p.br_from[e];
+        const double w = vk * V[j] * p.br_b[e];
+        const double d = tk - th[j];
+        acc += half ? -w * cos(d) : w * sin(d);
+    }
+    double r;
+    if (half == 0) {
+        const double Pk = p.P[k];
+        const double g = p.gfac[s];
+        const double spec = (g != 0.0 && Pk > 0.0) ? Pk + Pk * g : Pk;
+        r = spec - acc;
+    } else {
+        const double taken = vk * vk * (p.diag_bpp[k] - cut) + acc;
+        r = p.Q[k] - taken;
+    }
+    p.rhs[o] = r / vk;
+}
+
+// state += the half-iteration's correction; accumulate its solve's work
+__global__ void fdpf_update_kernel(FdpfParams p, int half) {
+    const int s = blockIdx.x;
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    if (k >= p.n_bus) return;
+    const size_t o = (size_t)s * p.n_bus + k;
+    if (half == 0)
+        p.theta[o] += p.dx[o];
+    else
+        p.V[o] += p.dx[o];
+    if (k == 0) {
+        p.iters[s] += p.it_step[s];
+        const int a = p.status[s], b = p.st_step[s];
+        const bool fail_b = b == kMaxIter || b == kBreakdown || b == kNonfinite;
+        const bool fail_a = a == kMaxIter || a == kBreakdown || a == kNonfinite || a == kBadOutage;
+        if (!fail_a && (fail_b || a == kConverged)) p.status[s] = b;
+    }
+}
+
+// islanded buses (and every bus of a bad outage id) report theta = 0, V = 1
+__global__ void fdpf_finish_kernel(FdpfParams p) {
+    const int s = blockIdx.x;
+    const int k = blockIdx.y * blockDim.x + threadIdx.x;
+    if (k >= p.n_bus) return;
+    const int c = p.outages[s];
+    const size_t o = (size_t)s * p.n_bus + k;
+    if (c < -1 || c >= p.m || fdpf_island(p, c, k)) {
+        p.theta[o] = 0.0;
+        p.V[o] = 1.0;
+    }
+    if (k == 0 && p.nogen[s] && p.status[s] == kConvergedIslanded) p.status[s] = kIslandedNoGen;
+}
+
 // out[j] = sum_r w[r] a[r * lda + j], rows summed in order (deterministic)
 __global__ void weighted_rows_kernel(int n_rows, int n_cols, const double *a, int lda, const double *w,
                                      double *out) {
@@ -570,6 +695,23 @@ hipError_t launch_overload_grads(const OverloadParams &prm, hipStream_t st) {
     if (prm.grad_x)
         hipLaunchKernelGGL(overload_grad_x_kernel, dim3(prm.n_out, (prm.m + tb - 1) / tb), dim3(tb), 0, st, prm);
     if (prm.grad_p) hipLaunchKernelGGL(overload_grad_p_kernel, dim3(prm.n_out), dim3(256), 0, st, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdpf(const FdpfParams &prm, int phase, int half, hipStream_t st) {
+    if (prm.n_out <= 0) return hipSuccess;
+    const int tb = 256;
+    const dim3 grid(prm.n_out, (prm.n_bus + tb - 1) / tb);
+    switch (phase) {
+        case 0:
+            hipLaunchKernelGGL(fdpf_start_kernel, grid, dim3(tb), 0, st, prm);
+            hipLaunchKernelGGL(fdpf_redispatch_kernel, dim3(prm.n_out), dim3(256), 0, st, prm);
+            break;
+        case 1: hipLaunchKernelGGL(fdpf_mismatch_kernel, grid, dim3(tb), 0, st, prm, half); break;
+        case 2: hipLaunchKernelGGL(fdpf_update_kernel, grid, dim3(tb), 0, st, prm, half); break;
+        case 3: hipLaunchKernelGGL(fdpf_finish_kernel, grid, dim3(tb), 0, st, prm); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

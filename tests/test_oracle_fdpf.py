@@ -1,0 +1,135 @@
+"""Pins of the oracle's fast-decoupled power flow."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+from oracle import fdpf
+
+
+def _reactive(g, seed=4):
+    rng = np.random.default_rng(seed)
+    Q = rng.normal(0, 0.2, g.n)
+    bsh = rng.uniform(0, 0.05, g.n)
+    return Q, bsh
+
+
+def test_injections_match_complex_power(grids):
+    """P + jQ = V conj(Y V) with the complex bus admittance matrix: series
+    admittance -j/x per branch, shunt admittance -j b_sh per bus (reactor)."""
+    g = grids["grid200"]
+    Q, bsh = _reactive(g)
+    rng = np.random.default_rng(1)
+    th = rng.normal(0, 0.3, g.n)
+    V = rng.uniform(0.9, 1.1, g.n)
+    for c in (-1, 7):
+        Y = np.zeros((g.n, g.n), complex)
+        for e in range(g.m):
+            if e == c:
+                continue
+            a, b = g.br_from[e], g.br_to[e]
+            y = -1j / g.x[e]
+            Y[a, a] += y
+            Y[b, b] += y
+            Y[a, b] -= y
+            Y[b, a] -= y
+        Y[np.diag_indices(g.n)] += -1j * bsh
+        U = V * np.exp(1j * th)
+        S = U * np.conj(Y @ U)
+        P, Qc = fdpf.injections(g, th, V, bsh, c)
+        np.testing.assert_allclose(P, S.real, rtol=0, atol=1e-10)
+        np.testing.assert_allclose(Qc, S.imag, rtol=0, atol=1e-10)
+
+
+def test_first_half_iteration_is_the_dc_solution(grids):
+    """From a flat start the network takes no active power, so the first
+    P-theta half-iteration gives exactly the DC angles B'^-1 P."""
+    g = grids["grid200"]
+    Q, bsh = _reactive(g)
+    th_dc, _ = oracle.base_case(g)
+    th, V, _ = fdpf.fdpf(g, g.P, Q, bsh, np.zeros(g.n), np.ones(g.n), -1, iters=1)
+    np.testing.assert_allclose(th, th_dc, rtol=1e-12, atol=1e-12)
+    assert V[0] == 1.0 and th[0] == 0.0
+
+
+def test_two_bus_converges_to_root():
+    """Two buses: the iteration's fixed point solves the two power-flow
+    equations, found independently with a library root finder."""
+    from scipy.optimize import fsolve
+
+    g = gridgen.hand_grid("two_bus")
+    x, b = g.x[0], 0.03
+    P1, Q1 = 0.8, 0.3
+    P = np.array([-P1, P1])
+    Q = np.array([0.0, Q1])
+    bsh = np.array([0.0, b])
+
+    def eqs(v):
+        t, V = v
+        return [V * np.sin(t) / x - P1, V * V * (1 / x + b) - V * np.cos(t) / x - Q1]
+
+    t_ref, V_ref = fsolve(eqs, [0.1, 1.0], xtol=1e-14)
+    th, V, _ = fdpf.fdpf(g, P, Q, bsh, np.zeros(2), np.ones(2), -1, iters=80)
+    assert th[1] == pytest.approx(t_ref, abs=1e-10)
+    assert V[1] == pytest.approx(V_ref, abs=1e-10)
+
+
+def test_mild_case_converges_to_power_flow_solution(grids):
+    """With light loading (injections and shunts at 2 % of the workload's
+    draws; at full size the shunts of every bus draw reactive power the
+    network cannot carry and the iteration has no solution to approach) the
+    iteration converges on the 200-bus grid and the converged state takes
+    exactly the specified P and Q."""
+    g = grids["grid200"]
+    Q, bsh = _reactive(g)
+    P, Qs, bs = 0.02 * g.P, 0.02 * Q, 0.02 * bsh
+    th, V, _ = fdpf.fdpf(g, P, Qs, bs, np.zeros(g.n), np.ones(g.n), -1, iters=60)
+    Pc, Qc = fdpf.injections(g, th, V, bs)
+    assert np.abs(Pc[1:] - P[1:]).max() < 1e-10
+    assert np.abs(Qc[1:] - Qs[1:]).max() < 1e-10
+
+
+def _without(g, keep_branch, keep_bus=None):
+    """The grid with only the given branches (and buses, relabelled)."""
+    f, t, x = g.br_from[keep_branch], g.br_to[keep_branch], g.x[keep_branch]
+    if keep_bus is None:
+        return dataclasses.replace(g, br_from=f.copy(), br_to=t.copy(), x=x.copy())
+    new = -np.ones(g.n, np.int64)
+    new[keep_bus] = np.arange(len(keep_bus))
+    return dataclasses.replace(g, n=len(keep_bus), br_from=new[f].astype(np.int32), br_to=new[t].astype(np.int32),
+                               x=x.copy(), P=g.P[keep_bus].copy(), pts=None)
+
+
+def test_outage_equals_deleted_branch(grids):
+    """An outage equals the same iteration on the grid with the branch gone."""
+    g = grids["grid200"]
+    Q, bsh = _reactive(g)
+    th0, V0 = fdpf.base_state(g, g.P, Q, bsh)
+    c = next(e for e in range(g.m) if not oracle.is_bridge(g, e))
+    th, V, isl = fdpf.fdpf(g, g.P, Q, bsh, th0, V0, c)
+    assert not isl.any()
+    keep = np.arange(g.m) != c
+    th2, V2, _ = fdpf.fdpf(_without(g, keep), g.P, Q, bsh, th0, V0, -1)
+    np.testing.assert_allclose(th, th2, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(V, V2, rtol=0, atol=1e-12)
+
+
+def test_islanding_outage_equals_main_component(grids):
+    """An islanding outage: the island reports theta = 0, V = 1, and the main
+    system equals the iteration on the main component as a grid of its own
+    with the re-dispatched injections."""
+    g = grids["grid200"]
+    Q, bsh = _reactive(g)
+    th0, V0 = fdpf.base_state(g, g.P, Q, bsh)
+    c = next(e for e in range(g.m) if oracle.is_bridge(g, e) and oracle.island_of(g, e).sum() >= 3)
+    th, V, isl = fdpf.fdpf(g, g.P, Q, bsh, th0, V0, c)
+    assert np.all(th[isl] == 0.0) and np.all(V[isl] == 1.0)
+    main = np.flatnonzero(~isl)
+    keep = (~isl[g.br_from]) & (~isl[g.br_to]) & (np.arange(g.m) != c)
+    sub = _without(g, keep, main)
+    Pp, _ = oracle.redispatch(g.P, isl)
+    th2, V2, _ = fdpf.fdpf(sub, Pp[main], Q[main], bsh[main], th0[main], V0[main], -1)
+    np.testing.assert_allclose(th[main], th2, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(V[main], V2, rtol=0, atol=1e-12)
