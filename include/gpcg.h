@@ -82,6 +82,8 @@ typedef struct {
     int32_t block;         /* scenarios per tile, one of 1,2,4,8,16,32,64; 0 = 64 */
     int32_t base_max_iter; /* iterations per base-case solve step; 0 = 20000 */
     int32_t lookahead;     /* rows the triangular-solve scheduler may look ahead; 0 = 256 */
+    int32_t zero_start;    /* 1: every scenario starts from x0 = 0 (the listing of Section III.A)
+                              instead of the base state (Section III.B); 0 = base state */
 } gpcg_options;
 
 /* Context facts, for logging and for the roofline accounting. */
@@ -309,6 +311,20 @@ int gpcg_weighted_rows(gpcg_t h, int32_t n_rows, int32_t n_cols, const double *a
 int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, const double *P, const double *Q,
               const double *theta0, const double *V0, int32_t n_outer, double tol, int32_t max_iter,
               double *theta_out, double *V_out, int32_t *iters_out, int32_t *status_out);
+
+/*
+ * Overload screening of solved scenarios (Section IV: the post-outage
+ * branch flows are the screening quantity): per scenario, the number of
+ * branches with |f_e| > F_e, the largest loading |f_e| / F_e and the branch
+ * that carries it (the lowest index among equals).
+ *   flows        device f64[n_out * m], e.g. flows_out of a solve.
+ *   flow_limit   device f64[m], F_e > 0.
+ *   count_out    device int32[n_out]; worst_out device f64[n_out];
+ *   worst_branch_out device int32[n_out] (-1 when every flow is 0).
+ * GPCG_E_ARG for NULL pointers.  Asynchronous on the context's stream.
+ */
+int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const double *flow_limit,
+                          int32_t *count_out, double *worst_out, int32_t *worst_branch_out);
 
 /*
  * The same computation with the plain per-scenario PCG: one scenario at a

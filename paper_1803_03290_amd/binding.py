@@ -29,7 +29,8 @@ class _Csr(C.Structure):
 
 
 class _Options(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("base_max_iter", C.c_int32), ("lookahead", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("base_max_iter", C.c_int32), ("lookahead", C.c_int32),
+                ("zero_start", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -66,6 +67,7 @@ SIGNATURES = {
     "gpcg_overload_gradients": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double, C.c_double, C.c_int32, _VP,
                                           _VP, _VP, _VP, _VP]),
     "gpcg_weighted_rows": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
+    "gpcg_screen_overloads": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "gpcg_fdpf": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP,
                             _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -161,6 +163,20 @@ def ilu0(A: Csr):
     return (Csr(lr, lc[: nl.value].copy(), lv[: nl.value].copy()), Csr(ur, uc[: nu.value].copy(), uv[: nu.value].copy()))
 
 
+def jacobi_factors(A: Csr):
+    """Factors of the Jacobi preconditioner M = diag(A) in the library's
+    factor format: L with no entries, U the diagonal (argument marshalling:
+    the diagonal is copied out of A's arrays)."""
+    n = len(A.rowptr) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(A.rowptr))
+    diag = A.val[A.col == rows]
+    if len(diag) != n:
+        raise ValueError("A must hold every diagonal entry once")
+    L = Csr(np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    U = Csr(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), diag)
+    return L, U
+
+
 def topology(n_bus, br_from, br_to):
     """gpcg_topology: bridge flags, DFS pre-order, subtree sizes, island intervals."""
     f, t = _i32(br_from), _i32(br_to)
@@ -180,11 +196,14 @@ def _ptr(t):
 class Context:
     """A device context (gpcg_setup / gpcg_destroy) for one grid and one
     matrix kind.  ``A``, ``L``, ``U`` default to the library's own assembly
-    and ILU(0) of the branch table."""
+    and ILU(0) of the branch table; ``precond="jacobi"`` passes L = 0 and
+    U = diag(A) instead (the Jacobi preconditioner of the GPCG listing,
+    Section III.B).  ``zero_start`` starts every scenario from x0 = 0 (the
+    listing of Section III.A) instead of the base state."""
 
     def __init__(self, n_bus, br_from, br_to, x, base_rhs=None, *, shunt=None, kind=KIND_BP, block=64,
                  theta_base=None, A: Csr | None = None, L: Csr | None = None, U: Csr | None = None, lookahead=0,
-                 stream=None):
+                 stream=None, precond="ilu0", zero_start=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -194,10 +213,15 @@ class Context:
         self.br_from, self.br_to, self.x = _i32(br_from), _i32(br_to), _f64(x)
         self.A = A if A is not None else assemble(n_bus, br_from, br_to, x, shunt)
         if L is None or U is None:
-            L, U = ilu0(self.A)
+            if precond == "jacobi":
+                L, U = jacobi_factors(self.A)
+            elif precond == "ilu0":
+                L, U = ilu0(self.A)
+            else:
+                raise ValueError(f"unknown preconditioner {precond!r}")
         self.L, self.U = L, U
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opt = _Options(kind, block, 0, lookahead)
+        opt = _Options(kind, block, 0, lookahead, 1 if zero_start else 0)
         a, l, u = self.A._c(), L._c(), U._c()
         h = C.c_void_p()
         rhs = None if base_rhs is None else _f64(base_rhs)
@@ -330,6 +354,22 @@ class Context:
         _check(self._lib.gpcg_fdpf(self._h, bpp._h, n_out, _ptr(outages), _ptr(P), _ptr(Q), _ptr(theta0), _ptr(V0),
                                    int(n_outer), float(tol), int(max_iter), _ptr(out["theta"]), _ptr(out["V"]),
                                    _ptr(out["iters"]), _ptr(out["status"])))
+        return out
+
+    def screen_overloads(self, flows, F):
+        """gpcg_screen_overloads: per scenario the overloaded-branch count, the
+        worst loading |f| / F and its branch (device tensors)."""
+        import torch
+
+        n_out = int(flows.shape[0])
+        dev = flows.device
+        out = {
+            "count": torch.empty(n_out, dtype=torch.int32, device=dev),
+            "worst": torch.empty(n_out, dtype=torch.float64, device=dev),
+            "worst_branch": torch.empty(n_out, dtype=torch.int32, device=dev),
+        }
+        _check(self._lib.gpcg_screen_overloads(self._h, n_out, _ptr(flows), _ptr(F), _ptr(out["count"]),
+                                               _ptr(out["worst"]), _ptr(out["worst_branch"])))
         return out
 
     def order(self, n_out) -> np.ndarray:

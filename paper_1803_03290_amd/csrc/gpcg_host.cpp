@@ -498,7 +498,7 @@ struct DevSchedule {
 struct gpcg_context {
     int device = 0;
     hipStream_t stream = nullptr;
-    int n_bus = 0, m = 0, n_r = 0, kind = GPCG_KIND_BP, S = 64, look = 256, bandwidth = 0;
+    int n_bus = 0, m = 0, n_r = 0, kind = GPCG_KIND_BP, S = 64, look = 256, bandwidth = 0, zero_start = 0;
     int nnz_a = 0, nnz_l = 0, nnz_u = 0;
     DevBuf<int32_t> a_rowptr, a_col, l_rowptr, l_col, u_rowptr, u_col;
     DevBuf<double> a_val, l_val, u_val, u_invdiag;
@@ -640,6 +640,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
     p.rhs_cols = rhs_cols;
     p.rhs_ld = rhs_ld;
+    p.zero_start = (!rhs_cols && h->zero_start) ? 1 : 0;
     const int32_t *pos = nullptr;
     if (S_ > 1 && n_out > S_) {
         // group scenarios of similar expected work into the same tiles
@@ -698,6 +699,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.rhs = rhs;
     o.rhs_cols = rhs_cols;
     o.rhs_ld = rhs_ld;
+    o.add_base = (!rhs_cols && !h->zero_start) ? 1 : 0;
     o.outages = outages;
     o.pos = pos;
     o.ws = h->ws.p;
@@ -885,6 +887,7 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->kind = o.kind;
         h->S = S;
         h->look = o.lookahead > 0 ? o.lookahead : 256;
+        h->zero_start = o.zero_start ? 1 : 0;
         h->bandwidth = bw;
         h->nnz_a = A->nnz;
         h->nnz_l = L->nnz;
@@ -1167,6 +1170,21 @@ int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, cons
             }
         }
         hip_check(gpcg::launch_fdpf(f, 3, 0, st), "fdpf finish");
+    });
+}
+
+int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const double *flow_limit,
+                          int32_t *count_out, double *worst_out, int32_t *worst_branch_out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
+        if (n_out == 0) return;
+        if (!flows || !flow_limit || !count_out || !worst_out || !worst_branch_out)
+            fail(GPCG_E_ARG, "a required pointer is NULL");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        hip_check(gpcg::launch_screen(n_out, h->m, flows, flow_limit, count_out, worst_out, worst_branch_out,
+                                      h->stream),
+                  "screening");
     });
 }
 

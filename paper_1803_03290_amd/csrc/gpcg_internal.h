@@ -73,6 +73,7 @@ struct PcgParams {
     // no re-dispatch
     const double *rhs_cols;
     int rhs_ld;
+    int zero_start;  // 1: start from x = 0 (r0 = P'_M), the result is theta itself
     // scenarios: tile position j solves scenario order[j] (NULL: j itself)
     const int32_t *outages;
     const int32_t *order;
@@ -96,6 +97,7 @@ struct OutParams {
     const double *theta_b, *rhs;
     const double *rhs_cols;  // per-scenario right-hand sides (then x = delta, no base state added)
     int rhs_ld;
+    int add_base;  // 1: x = theta_b + delta (warm start from the base state)
     const int32_t *outages;
     const int32_t *pos;  // tile position of each scenario (NULL: the scenario index)
     const double *ws;
@@ -195,6 +197,9 @@ hipError_t launch_overload_grads(const OverloadParams &prm, hipStream_t st);
 // 1 mismatch of half h into rhs; 2 state += dx for half h and accumulate
 // the solve's iterations and status; 3 islands to theta = 0, V = 1
 hipError_t launch_fdpf(const FdpfParams &prm, int phase, int half, hipStream_t st);
+// per scenario: branches with |f| > F, the largest |f| / F and its branch
+hipError_t launch_screen(int n_out, int m, const double *flows, const double *F, int32_t *count, double *worst,
+                         int32_t *worst_branch, hipStream_t st);
 // out[j] = sum_r w[r] a[r * lda + j]
 hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda, const double *w, double *out,
                                 hipStream_t st);

@@ -51,7 +51,7 @@ __global__ void theta_out_kernel(OutParams p) {
     if (k > 0 && !in && !bad) {
         const int j = p.pos ? p.pos[s] : s;
         const int tile = j / p.S, sc = j % p.S;
-        th = (p.rhs_cols ? 0.0 : p.theta_b[k]) + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
+        th = (p.add_base ? p.theta_b[k] : 0.0) + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
     }
     p.x_out[(size_t)s * p.n_bus + k] = th;
     if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
@@ -597,6 +597,49 @@ __global__ void fdpf_finish_kernel(FdpfParams p) {
     if (k == 0 && p.nogen[s] && p.status[s] == kConvergedIslanded) p.status[s] = kIslandedNoGen;
 }
 
+// Overload screening: per scenario the count of |f_e| > F_e, the largest
+// loading |f_e| / F_e and the lowest branch index that reaches it.
+__global__ void __launch_bounds__(256) screen_kernel(int m, const double *flows, const double *F, int32_t *count,
+                                                     double *worst, int32_t *worst_branch) {
+    __shared__ int sc[256];
+    __shared__ double sw[256];
+    __shared__ int sb[256];
+    const int s = blockIdx.x;
+    const double *f = flows + (size_t)s * m;
+    int n = 0, wb = -1;
+    double w = 0.0;
+    for (int e = threadIdx.x; e < m; e += blockDim.x) {
+        const double a = fabs(f[e]);
+        if (a > F[e]) ++n;
+        const double l = a / F[e];
+        if (l > w) {  // e increases within a thread: the first maximum wins
+            w = l;
+            wb = e;
+        }
+    }
+    sc[threadIdx.x] = n;
+    sw[threadIdx.x] = w;
+    sb[threadIdx.x] = wb;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const int t = threadIdx.x + o;
+            sc[threadIdx.x] += sc[t];
+            if (sw[t] > sw[threadIdx.x] || (sw[t] == sw[threadIdx.x] && sb[t] >= 0 &&
+                                            (sb[threadIdx.x] < 0 || sb[t] < sb[threadIdx.x]))) {
+                sw[threadIdx.x] = sw[t];
+                sb[threadIdx.x] = sb[t];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        count[s] = sc[0];
+        worst[s] = sw[0];
+        worst_branch[s] = sb[0];
+    }
+}
+
 // out[j] = sum_r w[r] a[r * lda + j], rows summed in order (deterministic)
 __global__ void weighted_rows_kernel(int n_rows, int n_cols, const double *a, int lda, const double *w,
                                      double *out) {
@@ -712,6 +755,13 @@ hipError_t launch_fdpf(const FdpfParams &prm, int phase, int half, hipStream_t s
         case 3: hipLaunchKernelGGL(fdpf_finish_kernel, grid, dim3(tb), 0, st, prm); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(int n_out, int m, const double *flows, const double *F, int32_t *count, double *worst,
+                         int32_t *worst_branch, hipStream_t st) {
+    if (n_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL(screen_kernel, dim3(n_out), dim3(256), 0, st, m, flows, F, count, worst, worst_branch);
     return hipGetLastError();
 }
 

@@ -470,10 +470,14 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
             if (!in_interval(p.pre_row[i], lo, hi)) {
                 const double Pk = p.rhs[i + 1];
                 const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
-                r0 = dPk + p.rho_b[i];
-                if (i == ic) r0 += corr;
-                if (i == jc) r0 -= corr;
                 const double b = Pk + dPk;
+                if (p.zero_start) {
+                    r0 = b;
+                } else {
+                    r0 = dPk + p.rho_b[i];
+                    if (i == ic) r0 += corr;
+                    if (i == jc) r0 -= corr;
+                }
                 bb += b * b;
             }
             rr += r0 * r0;

@@ -506,3 +506,64 @@ def test_fdpf_grid10k_sampled(gp, grids):
         th, V, _ = fdpf.fdpf(g, P, Q, bsh, th_b, V_b, int(c))
         assert np.abs(res["theta"][c] - th).max() <= 1e-8, (c, np.abs(res["theta"][c] - th).max())
         assert np.abs(res["V"][c] - V).max() <= 1e-8, (c, np.abs(res["V"][c] - V).max())
+
+
+# ------------------------------------------------ ablations (Jacobi, x0 = 0)
+
+
+def test_jacobi_preconditioner_grid200(gp, grids):
+    """The Jacobi preconditioner of the GPCG listing (z = r / diag): every
+    outage against the direct solve, iterations on a sample against the
+    oracle's textbook PCG with M = diag(A) in the same correction form."""
+    import scipy.sparse as sp
+
+    g = grids["grid200"]
+    thb, A = oracle.base_case(g)
+    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=16, precond="jacobi")
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res)
+    Lj = sp.csr_matrix(A.shape)
+    Uj = sp.diags(A.diagonal()).tocsr()
+    for c in outs[::10]:
+        p = oracle.scenario_pcg(g, c, A, Lj, Uj, thb, tol=1e-12)
+        assert _iters_close(res["iters"][c], p["iters"]), (c, res["iters"][c], p["iters"])
+
+
+def test_zero_start_grid200(gp, grids):
+    """x0 = 0 (the listing of Section III.A) instead of the base state: every
+    outage against the direct solve; iterations on a sample against the
+    textbook PCG from x0 = 0 on the re-dispatched right-hand side."""
+    g = grids["grid200"]
+    _, A = oracle.base_case(g)
+    L, U = oracle.ilu0(A)
+    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=16, zero_start=True)
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res)
+    for c in outs[::7]:
+        d = oracle.scenario(g, c, A)
+        mask = ~d["island"][1:]
+        Ac = oracle.outage_matrix(g, A, c)
+        _, k, _, _ = oracle.pcg_textbook(Ac, np.where(mask, d["Pp"][1:], 0.0), L, U, mask=mask, tol=1e-12)
+        assert _iters_close(res["iters"][c], k), (c, res["iters"][c], k)
+
+
+def test_overload_screening_grid2k(gp, grids):
+    """Screening of all outages of the 2k grid against limits from the base
+    flows: counts, worst loading and worst branch bit-exact against the
+    same comparisons made on the returned flows (the flows themselves are
+    checked against the oracle elsewhere)."""
+    g = grids["grid2k"]
+    ctx = _ctx(gp, g, block=4)
+    base = _run(gp, ctx, g, [-1])
+    F = 1.0 * np.abs(base["flows"][0]) + 0.05
+    res = _run(gp, ctx, g, np.arange(g.m))
+    flows = torch.tensor(res["flows"], device="cuda")
+    sc = ctx.screen_overloads(flows, torch.tensor(F, device="cuda"))
+    torch.cuda.synchronize()
+    load = np.abs(res["flows"]) / F
+    np.testing.assert_array_equal(sc["count"].cpu().numpy(), (np.abs(res["flows"]) > F).sum(axis=1))
+    np.testing.assert_array_equal(sc["worst"].cpu().numpy(), load.max(axis=1))
+    np.testing.assert_array_equal(sc["worst_branch"].cpu().numpy(), load.argmax(axis=1))
+    assert sc["count"].cpu().numpy().max() > 0
