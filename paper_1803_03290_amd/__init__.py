@@ -25,3 +25,5 @@ from .binding import (  # noqa: F401
     topology,
 )
 from .overload import OverloadLoss, overload_loss  # noqa: F401,E402
+from .binding import Batch, batch_tune  # noqa: F401,E402
+from .autotune import BlockTuner  # noqa: F401,E402

@@ -68,6 +68,12 @@ SIGNATURES = {
                                           _VP, _VP, _VP, _VP]),
     "gpcg_weighted_rows": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
     "gpcg_screen_overloads": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_batch_create": (C.c_int, [C.POINTER(_VP), C.c_int32, _VP, C.c_int32, _i32p, _VP, _VP, C.c_double,
+                                    C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_batch_run": (C.c_int, [_VP]),
+    "gpcg_batch_destroy": (None, [_VP]),
+    "gpcg_batch_tune": (C.c_int, [C.c_int32, _VP, _i32p, _VP, _VP, C.c_double, C.c_int32, C.c_int32, _i32p,
+                                  C.c_int32, _f64p]),
     "gpcg_fdpf": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP,
                             _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -391,3 +397,79 @@ class Context:
     def spmm(self, outages, p, q, pq=None):
         """gpcg_spmm on tile-interleaved device blocks."""
         _check(self._lib.gpcg_spmm(self._h, int(outages.shape[0]), _ptr(outages), _ptr(p), _ptr(q), _ptr(pq)))
+
+
+def _ptr_array(tensors):
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+class Batch:
+    """gpcg_batch_create / gpcg_batch_run / gpcg_batch_destroy: the scenario
+    lists of several contexts (different grids, one device and stream)
+    solved by one launch of the tile kernel, captured in a HIP graph.
+    ``outages`` and ``rhs`` are lists of device tensors (int32[n_out_i],
+    float64[n_bus_i]); the batch keeps them and re-reads their contents on
+    every ``run()``.  ``out[i]`` holds grid i's device output tensors."""
+
+    def __init__(self, contexts, outages, rhs, block, tol=1e-12, max_iter=20000, *, flows=True, resid=True):
+        import torch
+
+        if not (len(contexts) == len(outages) == len(rhs)):
+            raise ValueError("one outage list and one right-hand side per context")
+        self._lib = lib()
+        self.contexts, self.outages, self.rhs = list(contexts), list(outages), list(rhs)
+        self.out = []
+        for ctx, o in zip(self.contexts, self.outages):
+            n = int(o.shape[0])
+            dev = o.device
+            self.out.append({
+                "x": torch.empty((n, ctx.n_bus), dtype=torch.float64, device=dev),
+                "flows": (torch.empty((n, ctx.m), dtype=torch.float64, device=dev)
+                          if flows and ctx.kind == KIND_BP else None),
+                "iters": torch.empty(n, dtype=torch.int32, device=dev),
+                "status": torch.empty(n, dtype=torch.int32, device=dev),
+                "resid": torch.empty(n, dtype=torch.float64, device=dev) if resid else None,
+            })
+        k = len(self.contexts)
+        ctxs = (C.c_void_p * k)(*[c._h.value for c in self.contexts])
+        n_outs = np.array([int(o.shape[0]) for o in self.outages], np.int32)
+        self._keep = (ctxs, n_outs)
+        h = C.c_void_p()
+        _check(self._lib.gpcg_batch_create(
+            C.byref(h), k, ctxs, int(block), _ip(n_outs), _ptr_array(self.outages), _ptr_array(self.rhs),
+            float(tol), int(max_iter), _ptr_array([d["x"] for d in self.out]),
+            _ptr_array([d["flows"] for d in self.out]), _ptr_array([d["iters"] for d in self.out]),
+            _ptr_array([d["status"] for d in self.out]), _ptr_array([d["resid"] for d in self.out])))
+        self._h = h
+        self.block = int(block)
+
+    def run(self):
+        _check(self._lib.gpcg_batch_run(self._h))
+        return self.out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gpcg_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_tune(contexts, outages, rhs, candidates=(4, 8, 16), tol=1e-12, max_iter=20000, reps=1):
+    """gpcg_batch_tune: milliseconds per batch solve for each candidate block."""
+    k = len(contexts)
+    ctxs = (C.c_void_p * k)(*[c._h.value for c in contexts])
+    n_outs = np.array([int(o.shape[0]) for o in outages], np.int32)
+    cand = np.array(candidates, np.int32)
+    ms = np.zeros(len(cand))
+    _check(lib().gpcg_batch_tune(k, ctxs, _ip(n_outs), _ptr_array(outages), _ptr_array(rhs), float(tol),
+                                 int(max_iter), len(cand), _ip(cand), int(reps), _fp(ms)))
+    return dict(zip((int(c) for c in cand), (float(v) for v in ms)))
+

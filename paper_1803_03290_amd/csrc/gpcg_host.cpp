@@ -520,7 +520,7 @@ struct gpcg_context {
     CsrH hA, hL, hU;                               // A, L, strict upper of U
     std::vector<double> h_invdiag;
     std::vector<int32_t> h_prerow;
-    std::unique_ptr<DevSchedule> sched_batched, sched_plain;
+    std::shared_ptr<DevSchedule> sched_batched, sched_plain;  // shared with batches that use them
     Topology topo;
     std::vector<double> theta_b_host;
     int base_iters = 0;
@@ -537,7 +537,7 @@ struct gpcg_context {
 
     DevSchedule &schedule_for(int S_) {
         const int R = gpcg::kWave / S_;
-        std::unique_ptr<DevSchedule> &slot = (S_ == 1) ? sched_plain : sched_batched;
+        std::shared_ptr<DevSchedule> &slot = (S_ == 1) ? sched_plain : sched_batched;
         if (slot && slot->R == R) return *slot;
         auto D = std::make_unique<DevSchedule>();
         D->R = R;
@@ -762,6 +762,209 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
                              h->stream),
               "copy");
     hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the scenario lists of several grids solved by one launch of the
+// tile kernel, captured once in a HIP graph and replayed.  A batch owns
+// everything a replay writes or reads that a later call on one of its
+// contexts could reallocate (workspace, scenario order, base residual,
+// re-dispatch factors) and holds a reference to the schedules it uses; the
+// contexts' matrices and branch tables are read in place, so the contexts
+// must outlive the batch.
+struct BatchGrid {
+    gpcg_context *ctx = nullptr;
+    std::shared_ptr<DevSchedule> sched;
+    int n_out = 0, tiles = 0;
+    const int32_t *outages = nullptr;
+    const double *rhs = nullptr;
+    double *x_out = nullptr, *flows_out = nullptr, *resid_out = nullptr;
+    int32_t *iters_out = nullptr, *status_out = nullptr;
+    DevBuf<double> ws, rho_b, gfac;
+    DevBuf<int32_t> order, pos;
+};
+
+struct BatchSpec {
+    int n = 0;
+    const gpcg_t *ctxs = nullptr;
+    const int32_t *n_outs = nullptr;
+    const int32_t *const *outages = nullptr;
+    const double *const *rhs = nullptr;
+    double *const *x_out = nullptr;
+    double *const *flows_out = nullptr;
+    double *const *resid_out = nullptr;
+    int32_t *const *iters_out = nullptr;
+    int32_t *const *status_out = nullptr;
+};
+
+}  // namespace
+
+struct gpcg_batch {
+    int device = 0, S = 1, ring = 1, total_tiles = 0, max_iter = 1;
+    double tol = 0.0;
+    hipStream_t stream = nullptr;
+    std::vector<std::unique_ptr<BatchGrid>> g;  // heaviest grid first
+    DevBuf<gpcg::PcgParams> params;
+    DevBuf<int32_t> tile_start;
+    hipStream_t outer = nullptr;  // the contexts' stream; the batch works on a stream of its own
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~gpcg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+// Build a batch without its graph: per grid the schedules for S, its own
+// workspace, the scenario order (once), the kernel parameters.
+std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, int max_iter) {
+    if (sp.n < 1) fail(GPCG_E_ARG, "a batch needs at least one context");
+    if (S < 1 || S > 64 || (S & (S - 1))) fail(GPCG_E_ARG, "block must be a power of two in [1, 64]");
+    if (max_iter < 1) fail(GPCG_E_ARG, "max_iter must be >= 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) fail(GPCG_E_ARG, "tol must be finite and >= 0");
+    auto b = std::make_unique<gpcg_batch>();
+    b->S = S;
+    b->tol = tol;
+    b->max_iter = max_iter;
+    for (int i = 0; i < sp.n; ++i) {
+        gpcg_context *h = sp.ctxs[i];
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        if (i == 0) {
+            b->device = h->device;
+            b->outer = h->stream;
+        } else if (h->device != b->device || h->stream != b->outer) {
+            fail(GPCG_E_ARG, "the contexts of a batch must share a device and a stream");
+        }
+        const int n_out = sp.n_outs[i];
+        if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
+        if (n_out && (!sp.outages[i] || !sp.rhs[i] || !sp.x_out[i] || !sp.iters_out[i] || !sp.status_out[i]))
+            fail(GPCG_E_ARG, "a required pointer is NULL");
+        if (sp.flows_out && sp.flows_out[i] && h->kind != GPCG_KIND_BP)
+            fail(GPCG_E_ARG, "flows are only defined for a B' context");
+        auto G = std::make_unique<BatchGrid>();
+        G->ctx = h;
+        G->n_out = n_out;
+        G->tiles = (n_out + S - 1) / S;
+        G->outages = sp.outages[i];
+        G->rhs = sp.rhs[i];
+        G->x_out = sp.x_out[i];
+        G->flows_out = sp.flows_out ? sp.flows_out[i] : nullptr;
+        G->resid_out = sp.resid_out ? sp.resid_out[i] : nullptr;
+        G->iters_out = sp.iters_out[i];
+        G->status_out = sp.status_out[i];
+        b->g.push_back(std::move(G));
+    }
+    hip_check(hipSetDevice(b->device), "hipSetDevice");
+    // a stream of the batch's own (a graph cannot be captured on the null
+    // stream), default priority, ordered against the contexts' stream
+    hip_check(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "batch stream");
+    hip_check(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "batch event");
+    hip_check(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "batch event");
+    hip_check(hipEventRecord(b->ev_in, b->outer), "event");
+    hip_check(hipStreamWaitEvent(b->stream, b->ev_in, 0), "stream wait");
+    // heaviest first: the tiles of big grids run longest
+    std::stable_sort(b->g.begin(), b->g.end(),
+                     [](const std::unique_ptr<BatchGrid> &x, const std::unique_ptr<BatchGrid> &y) {
+                         return x->ctx->n_r > y->ctx->n_r;
+                     });
+    std::vector<gpcg::PcgParams> prm;
+    std::vector<int32_t> start(1, 0);
+    for (auto &G : b->g) {
+        gpcg_context *h = G->ctx;
+        h->schedule_for(S);
+        G->sched = (S == 1) ? h->sched_plain : h->sched_batched;
+        b->ring = std::max(b->ring, G->sched->ring_max());
+        G->ws.alloc(std::max<size_t>(1, (size_t)G->tiles * gpcg::kVectors * (size_t)(h->n_r + 1) * S));
+        G->rho_b.alloc(h->n_r);
+        G->gfac.alloc(std::max(G->n_out, 1));
+        gpcg::PcgParams p = h->params(*G->sched, G->outages, G->n_out, G->rhs, tol, max_iter, G->iters_out,
+                                      G->status_out);
+        p.ws = G->ws.p;
+        p.rho_b = G->rho_b.p;
+        p.gfac_out = G->gfac.p;
+        p.zero_start = h->zero_start;
+        if (S > 1 && G->n_out > S) {
+            const int n = G->n_out;
+            DevBuf<uint32_t> keys, keys_sorted;
+            DevBuf<int32_t> iota;
+            DevBuf<char> temp;
+            keys.alloc(n);
+            keys_sorted.alloc(n);
+            iota.alloc(n);
+            G->order.alloc(n);
+            G->pos.alloc(n);
+            const size_t tb = gpcg::sort_temp_bytes(n);
+            temp.alloc(std::max<size_t>(tb, 1));
+            hip_check(gpcg::launch_order(n, G->outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
+                                         h->isl_hi.p, h->theta_b.p, keys.p, keys_sorted.p, iota.p, G->order.p,
+                                         G->pos.p, temp.p, tb, b->stream),
+                      "scenario ordering");
+            hip_check(hipStreamSynchronize(b->stream), "ordering");
+            p.order = G->order.p;
+        }
+        prm.push_back(p);
+        start.push_back(start.back() + G->tiles);
+    }
+    b->total_tiles = start.back();
+    b->params.upload(prm.data(), prm.size(), b->stream);
+    b->tile_start.upload(start.data(), start.size(), b->stream);
+    hip_check(hipStreamSynchronize(b->stream), "batch upload");
+    return b;
+}
+
+// Everything one solve of the batch enqueues (what the graph captures):
+// kernels only, no memory set or copy nodes.
+void batch_enqueue(gpcg_batch *b) {
+    for (auto &G : b->g) {
+        gpcg_context *h = G->ctx;
+        if (G->n_out == 0 || h->zero_start) continue;
+        hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, G->rhs,
+                                             G->rho_b.p, b->stream),
+                  "base residual");
+    }
+    hip_check(gpcg::launch_pcg_multi(b->params.p, b->tile_start.p, (int)b->g.size(), b->S, b->total_tiles, b->ring,
+                                     b->stream),
+              "batch launch");
+    for (auto &G : b->g) {
+        gpcg_context *h = G->ctx;
+        if (G->n_out == 0) continue;
+        gpcg::OutParams o{};
+        o.n_r = h->n_r;
+        o.n_bus = h->n_bus;
+        o.m = h->m;
+        o.kind = h->kind;
+        o.S = b->S;
+        o.n_out = G->n_out;
+        o.a_rowptr = h->a_rowptr.p;
+        o.a_col = h->a_col.p;
+        o.a_val = h->a_val.p;
+        o.br_from = h->br_from.p;
+        o.br_to = h->br_to.p;
+        o.br_x = h->br_x.p;
+        o.br_b = h->br_b.p;
+        o.pre_bus = h->pre_bus.p;
+        o.isl_lo = h->isl_lo.p;
+        o.isl_hi = h->isl_hi.p;
+        o.theta_b = h->theta_b.p;
+        o.rhs = G->rhs;
+        o.add_base = h->zero_start ? 0 : 1;
+        o.outages = G->outages;
+        o.pos = G->order.p ? G->pos.p : nullptr;
+        o.ws = G->ws.p;
+        o.status = G->status_out;
+        o.gfac = G->gfac.p;
+        o.x_out = G->x_out;
+        o.flows_out = G->flows_out;
+        o.resid_out = G->resid_out;
+        o.island_out = nullptr;
+        hip_check(gpcg::launch_outputs(o, b->stream), "batch outputs");
+    }
 }
 
 }  // namespace
@@ -1185,6 +1388,114 @@ int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const do
         hip_check(gpcg::launch_screen(n_out, h->m, flows, flow_limit, count_out, worst_out, worst_branch_out,
                                       h->stream),
                   "screening");
+    });
+}
+
+int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int32_t block, const int32_t *n_outs,
+                      const int32_t *const *outages, const double *const *rhs, double tol, int32_t max_iter,
+                      double *const *x_out, double *const *flows_out, int32_t *const *iters_out,
+                      int32_t *const *status_out, double *const *resid_out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out || !ctxs || !n_outs || !outages || !rhs || !x_out || !iters_out || !status_out)
+            fail(GPCG_E_ARG, "a required pointer is NULL");
+        BatchSpec sp;
+        sp.n = n_ctx;
+        sp.ctxs = ctxs;
+        sp.n_outs = n_outs;
+        sp.outages = outages;
+        sp.rhs = rhs;
+        sp.x_out = x_out;
+        sp.flows_out = flows_out;
+        sp.resid_out = resid_out;
+        sp.iters_out = iters_out;
+        sp.status_out = status_out;
+        auto b = batch_build(sp, block, tol, max_iter);
+        // one eager solve (results valid at once), then the same work captured
+        batch_enqueue(b.get());
+        hip_check(hipStreamSynchronize(b->stream), "batch first solve");
+        hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+            batch_enqueue(b.get());
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(b->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(b->stream, &b->graph), "end capture");
+        hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+        hip_check(hipEventRecord(b->ev_out, b->stream), "event");
+        hip_check(hipStreamWaitEvent(b->outer, b->ev_out, 0), "stream wait");
+        *out = b.release();
+    });
+}
+
+int gpcg_batch_run(gpcg_batch_t b) {
+    return guarded([&] {
+        if (!b) fail(GPCG_E_ARG, "batch is NULL");
+        hip_check(hipSetDevice(b->device), "hipSetDevice");
+        hip_check(hipEventRecord(b->ev_in, b->outer), "event");
+        hip_check(hipStreamWaitEvent(b->stream, b->ev_in, 0), "stream wait");
+        hip_check(hipGraphLaunch(b->exec, b->stream), "graph launch");
+        hip_check(hipEventRecord(b->ev_out, b->stream), "event");
+        hip_check(hipStreamWaitEvent(b->outer, b->ev_out, 0), "stream wait");
+    });
+}
+
+void gpcg_batch_destroy(gpcg_batch_t b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, const int32_t *const *outages,
+                    const double *const *rhs, double tol, int32_t max_iter, int32_t n_cand, const int32_t *cand,
+                    int32_t reps, double *ms_out) {
+    return guarded([&] {
+        if (!ctxs || !n_outs || !outages || !rhs || !cand || !ms_out) fail(GPCG_E_ARG, "a required pointer is NULL");
+        if (n_ctx < 1 || n_cand < 1 || reps < 1) fail(GPCG_E_ARG, "need contexts, candidates and reps >= 1");
+        // scratch outputs shared by the candidates
+        std::vector<DevBuf<double>> xs(n_ctx);
+        std::vector<DevBuf<int32_t>> its(n_ctx), sts(n_ctx);
+        std::vector<double *> xp(n_ctx);
+        std::vector<int32_t *> ip(n_ctx), spp(n_ctx);
+        for (int i = 0; i < n_ctx; ++i) {
+            if (!ctxs[i]) fail(GPCG_E_ARG, "context is NULL");
+            const size_t n = std::max(1, n_outs[i]);
+            xs[i].alloc(n * ctxs[i]->n_bus);
+            its[i].alloc(n);
+            sts[i].alloc(n);
+            xp[i] = xs[i].p;
+            ip[i] = its[i].p;
+            spp[i] = sts[i].p;
+        }
+        BatchSpec sp;
+        sp.n = n_ctx;
+        sp.ctxs = ctxs;
+        sp.n_outs = n_outs;
+        sp.outages = outages;
+        sp.rhs = rhs;
+        sp.x_out = xp.data();
+        sp.iters_out = ip.data();
+        sp.status_out = spp.data();
+        for (int k = 0; k < n_cand; ++k) {
+            auto b = batch_build(sp, cand[k], tol, max_iter);
+            batch_enqueue(b.get());  // warm-up
+            hipEvent_t e0, e1;
+            hip_check(hipEventCreate(&e0), "event");
+            hip_check(hipEventCreate(&e1), "event");
+            hip_check(hipEventRecord(e0, b->stream), "event");
+            for (int r = 0; r < reps; ++r) batch_enqueue(b.get());
+            hip_check(hipEventRecord(e1, b->stream), "event");
+            hip_check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            ms_out[k] = ms / reps;
+        }
     });
 }
 

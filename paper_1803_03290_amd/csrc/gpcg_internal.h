@@ -173,6 +173,11 @@ struct FdpfParams {
 // Launchers (launch_pcg in gpcg_tile.hip, the rest in gpcg_kernels.hip).  They
 // return hipSuccess or the launch error.
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st);
+// several grids in one launch: grids[g] (device) solves tiles
+// [tile_start[g], tile_start[g + 1]) of the launch (tile_start device,
+// n_grids + 1 entries); ring_rows = the largest ring of any grid
+hipError_t launch_pcg_multi(const PcgParams *grids, const int *tile_start, int n_grids, int S, int n_tiles,
+                            int ring_rows, hipStream_t st);
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st);
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
                                 const double *theta_b, const double *rhs, double *rho, hipStream_t st);

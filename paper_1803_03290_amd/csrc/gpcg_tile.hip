@@ -395,13 +395,11 @@ __device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, doub
 // ---------------------------------------------------------------------------
 // The tile kernel: init, then PCG iterations until every column stops.
 template <int S, int D, int DP>
-__global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
+__device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, double *ring) {
     constexpr int R = kWave / S;
-    extern __shared__ double ring[];
     const int lane = threadIdx.x;
     const int sc = lane % S;
     const int rs = lane / S;
-    const int tile = blockIdx.x + p.tile0;
     const int posn = tile * S + sc;  // tile position of this column
     const bool valid = posn < p.n_out;
     const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
@@ -569,6 +567,28 @@ __global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
     }
 }
 
+// One grid: work-group b solves tile tile0 + b.
+template <int S, int D, int DP>
+__global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
+    extern __shared__ double ring[];
+    pcg_tile<S, D, DP>(p, blockIdx.x + p.tile0, ring);
+}
+
+// Several grids in one launch (the uneven batch): work-group b solves tile
+// tile0 + b - tile_start[g] of grid g, tile_start ascending with
+// tile_start[0] = 0.  Grids are ordered by the caller, heaviest first, so
+// the dispatcher hands out the longest tiles before the short ones.
+template <int S, int D, int DP>
+__global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, const int *tile_start,
+                                                          int n_grids) {
+    extern __shared__ double ring[];
+    const int b = blockIdx.x;
+    int g = 0;
+    while (g + 1 < n_grids && tile_start[g + 1] <= b) ++g;
+    const PcgParams &p = grids[g];
+    pcg_tile<S, D, DP>(p, p.tile0 + b - tile_start[g], ring);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -584,6 +604,34 @@ static hipError_t launch_pcg_s(const PcgParams &prm, int n_tiles, size_t lds, hi
     }
     hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, prm);
     return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_multi_s(const PcgParams *grids, const int *tile_start, int n_grids, int n_tiles, size_t lds,
+                                 hipStream_t st) {
+    auto kern = pcg_multi_kernel<S, kPrefetch, kPrefetchProd>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, grids, tile_start, n_grids);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_multi(const PcgParams *grids, const int *tile_start, int n_grids, int S, int n_tiles,
+                            int ring_rows, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
+    switch (S) {
+        case 1: return launch_multi_s<1>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 2: return launch_multi_s<2>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 4: return launch_multi_s<4>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 8: return launch_multi_s<8>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 16: return launch_multi_s<16>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 32: return launch_multi_s<32>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 64: return launch_multi_s<64>(grids, tile_start, n_grids, n_tiles, lds, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st) {
