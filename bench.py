@@ -269,6 +269,91 @@ def fdpf_measure(gp, torch, grid, S: int = 16, scale: float = 1e-4, n_outer: int
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
 
 
+def ablation_measure(gp, torch, grid, S: int, tol: float, max_iter: int, steps: int = 3):
+    """The paper's own alternatives on the headline workload, same kernels:
+    the Jacobi preconditioner of the GPCG listing and the zero start of the
+    PCG listing, against the base-case ILU(0) and the base-state start."""
+    import numpy as np
+
+    dev = torch.device("cuda", 0)
+    outs = torch.arange(grid.m, dtype=torch.int32, device=dev)
+    rhs = torch.tensor(grid.P, dtype=torch.float64, device=dev)
+    res = {}
+    for name, kw in (("jacobi", dict(precond="jacobi")), ("zero_start", dict(zero_start=True))):
+        ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=S, **kw)
+        out = ctx.solve(outs, rhs, tol=tol, max_iter=max_iter)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.solve(outs, rhs, tol=tol, max_iter=max_iter, out=out)
+            e1.record(ctx.stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        it = out["iters"].cpu().numpy()
+        res[name] = {"value": grid.m / (ms * 1e-3), "unit": "scenarios/s", "ms": ms,
+                     "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                     "max_true_rel_residual": float(out["resid"].max().item())}
+    return res
+
+
+UNEVEN = ("uneven500", "uneven1000", "uneven2000", "uneven3000", "uneven5000", "uneven8000", "uneven12000",
+          "uneven20000")
+
+
+def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN):
+    """The uneven workload: all outages of eight grids (500 to 20,000 buses)
+    in one graph-captured launch; the block is picked by the autotuner
+    (blocks 4, 8 and 16, one timed solve each).  Timed with HIP events on the
+    contexts' stream around ``reps`` graph replays."""
+    import numpy as np
+
+    import gridgen
+
+    def progress(msg):
+        print(f"[batch] {msg}", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    grids, ctxs = [], []
+    for n in names:
+        t0 = time.perf_counter()
+        g = gridgen.make_grid(n)
+        t1 = time.perf_counter()
+        ctxs.append(gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=8))
+        grids.append(g)
+        progress(f"{n}: grid {t1 - t0:.1f} s, context {time.perf_counter() - t1:.1f} s")
+    outs = [torch.arange(g.m, dtype=torch.int32, device=dev) for g in grids]
+    rhs = [torch.tensor(g.P, dtype=torch.float64, device=dev) for g in grids]
+    tune_ms = {}
+    for cand in (4, 8, 16):  # the autotuner's search, one candidate per call so that progress shows
+        tune_ms.update(gp.batch_tune(ctxs, outs, rhs, (cand,), tol, max_iter))
+        progress(f"block {cand}: {tune_ms[cand]:.1f} ms per solve")
+    S = min(tune_ms, key=tune_ms.get)
+    b = gp.Batch(ctxs, outs, rhs, block=S, tol=tol, max_iter=max_iter, flows=True)
+    b.run()
+    torch.cuda.synchronize()
+    progress("batch built and captured")
+    stream = ctxs[0].stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = sum(g.m for g in grids)
+    resid = max(float(d["resid"].max().item()) for d in b.out)
+    st = np.concatenate([d["status"].cpu().numpy() for d in b.out])
+    b.close()
+    return {"workload": f"uneven batch: {len(grids)} grids of {grids[0].n} to {grids[-1].n} buses, all {n} outages "
+                        f"in one graph-captured launch, tol {tol:g}",
+            "value": n / (ms * 1e-3), "unit": "scenarios/s", "ms": ms, "block": S,
+            "tuner_ms_per_solve": tune_ms, "max_true_rel_residual": resid,
+            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -294,6 +379,10 @@ def main():
     ap.add_argument("--adjoint-block", type=int, default=16)
     ap.add_argument("--adjoint-only", action="store_true", help="only the overload-gradient measurement")
     ap.add_argument("--no-fdpf", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="also run the uneven multi-grid batch (72,100 outages of eight grids; several minutes)")
+    ap.add_argument("--batch-only", action="store_true", help="only the uneven multi-grid batch")
     ap.add_argument("--fdpf-workload", default="grid10k", help="grid of the power-flow measurement")
     ap.add_argument("--fdpf-only", action="store_true", help="only the power-flow measurement")
     args = ap.parse_args()
@@ -346,6 +435,9 @@ def main():
 
     if args.spmm_only:
         print(json.dumps(spmm_measure(gp, torch, aux_grid(args.spmm_workload), args.spmm_block)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(batch_measure(gp, torch, args.tol, args.max_iter)), flush=True)
         return
     if args.fdpf_only:
         print(json.dumps(fdpf_measure(gp, torch, aux_grid(args.fdpf_workload))), flush=True)
@@ -426,6 +518,8 @@ def main():
     adj = None if args.no_adjoint else adjoint_measure(gp, torch, aux_grid(args.adjoint_workload),
                                                        args.adjoint_block)
     pf = None if args.no_fdpf else fdpf_measure(gp, torch, aux_grid(args.fdpf_workload))
+    abl = None if args.no_ablations else ablation_measure(gp, torch, grid, S, args.tol, args.max_iter)
+    bat = batch_measure(gp, torch, args.tol, args.max_iter) if args.batch else None
 
     value = m / (ms_step * 1e-3)
     st_counts = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
@@ -459,6 +553,8 @@ def main():
         "spmm": spmm,
         "adjoint": adj,
         "fdpf": pf,
+        "ablations": abl,
+        "batch": bat,
         "cpu_baseline": cpu,
         "verify": {
             "status_counts": st_counts,
