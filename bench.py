@@ -390,7 +390,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the scenarios are independent, so more GPUs would each run the "
-              "same kernel on a share of the outage list (see DESIGN.md); run with --gpus 1.", file=sys.stderr)
+              "same kernel on a share of the outage list; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,6 +1,6 @@
 """GPU parity tests: the device library (through its C ABI) against the oracle.
 
-Bars (written here, derived in the design doc):
+Bars (each derived from the arithmetic it checks):
   * angles: |theta_gpu - theta_oracle|_inf <= 1e-8 rad;
   * flows:  |f_gpu - f_oracle| * x_e <= 2e-8;
   * island flags, bridge flags and scenario status: bit-exact;
