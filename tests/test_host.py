@@ -107,3 +107,50 @@ def test_errors_are_reported():
     with pytest.raises(gp.GpcgError) as e:
         gp.assemble(3, [0, 1], [1, 2], [0.1, -0.1])
     assert e.value.code == -1
+
+
+def test_jacobi_factors_are_the_diagonal(grids):
+    """The Jacobi preconditioner's factor pair: L without entries, U = diag(A),
+    in the library's factor format."""
+    import scipy.sparse as sp
+
+    g = grids["grid200"]
+    A = binding.assemble(g.n, g.br_from, g.br_to, g.x)
+    L, U = binding.jacobi_factors(A)
+    assert L.nnz == 0 and len(L.rowptr) == A.n + 1
+    np.testing.assert_array_equal(U.rowptr, np.arange(A.n + 1))
+    np.testing.assert_array_equal(U.col, np.arange(A.n))
+    np.testing.assert_array_equal(U.val, sp.csr_matrix(A.to_scipy()).diagonal())
+
+
+def test_block_tuner_caches_and_persists(tmp_path, monkeypatch):
+    """The autotuner keeps the fastest candidate per set of grids, answers
+    repeated questions from its table and reloads it from its JSON file."""
+    from paper_1803_03290_amd import autotune
+
+    class FakeCtx:
+        def __init__(self, n):
+            self.n_bus, self.kind = n, 0
+            self.br_from = np.arange(n - 1, dtype=np.int32)
+            self.br_to = np.arange(1, n, dtype=np.int32)
+            self.x = np.full(n - 1, 0.1)
+
+    class FakeOut:
+        shape = (7,)
+
+    calls = []
+
+    def fake_tune(ctxs, outs, rhs, cands, tol, max_iter, reps):
+        calls.append(tuple(cands))
+        return {c: {4: 3.0, 8: 1.5, 16: 2.0}[c] for c in cands}
+
+    monkeypatch.setattr(autotune, "batch_tune", fake_tune)
+    path = str(tmp_path / "tune.json")
+    t = autotune.BlockTuner(path)
+    ctxs = [FakeCtx(5), FakeCtx(9)]
+    outs = [FakeOut(), FakeOut()]
+    assert t.best(ctxs, outs, None, (4, 8, 16)) == 8
+    assert t.best(ctxs, outs, None, (4, 8, 16)) == 8 and len(calls) == 1
+    t2 = autotune.BlockTuner(path)
+    assert t2.best(ctxs, outs, None, (4, 8, 16)) == 8 and len(calls) == 1
+    assert t2.best(ctxs, outs, None, (4, 8, 16), tol=1e-10) == 8 and len(calls) == 2  # another key
