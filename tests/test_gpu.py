@@ -194,16 +194,18 @@ def test_spmm_against_numpy(gp, grids):
 # ---------------------------------------------------- 2,000-bus grid
 
 
-def test_grid2k_all_outages_batched(gp, grids):
-    """The benchmark workload at its full size and launch configuration:
-    every island flag checked bit-exact, angles and flows on a seeded sample
-    of 120 outages, iterations on 12."""
+@pytest.mark.parametrize("block,tol", [(64, 1e-12), (4, 5e-11)])
+def test_grid2k_all_outages_batched(gp, grids, block, tol):
+    """The benchmark workload at its full size; block 4 with the recursive
+    stop at 5e-11 is the launch the benchmark times.  Every island flag
+    checked bit-exact and every true residual against the bar, angles and
+    flows on a seeded sample of 120 outages, iterations on 12."""
     g = grids["grid2k"]
     thb, A = oracle.base_case(g)
     L, U = oracle.ilu0(A)
-    ctx = _ctx(gp, g, block=64)
+    ctx = _ctx(gp, g, block=block)
     outs = np.arange(g.m)
-    res = _run(gp, ctx, g, outs)
+    res = _run(gp, ctx, g, outs, tol=tol)
     isb, _ = ctx.base()
     for c in outs:
         np.testing.assert_array_equal(res["island"][c].astype(bool), oracle.island_of(g, int(c)))
@@ -212,8 +214,35 @@ def test_grid2k_all_outages_batched(gp, grids):
     sample = np.sort(rng.choice(g.m, 120, replace=False))
     _check_against_direct(g, A, sample, {k: (v[sample] if v is not None else None) for k, v in res.items()})
     for c in sample[:12]:
-        p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=1e-12)
+        p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=tol)
         assert _iters_close(res["iters"][c], p["iters"]), (c, res["iters"][c], p["iters"])
+
+
+# -------------------------------------------------- 10,000-bus grid, B'
+
+
+def test_grid10k_all_outages(gp, grids):
+    """Every outage of the 10,000-bus grid in one launch (block 16, the
+    recursive stop at 5e-11): island flags of all 13,500 outages bit-exact
+    against the brute-force component pass, every status and true residual
+    against the bar, angles and flows on a seeded sample of 60."""
+    g = grids["grid10k"]
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=16)
+    outs = np.arange(g.m)
+    res = _run(gp, ctx, g, outs, tol=5e-11)
+    assert res["resid"].max() <= RESID_TOL
+    for c in outs:
+        isl = oracle.island_of(g, int(c))
+        np.testing.assert_array_equal(res["island"][c].astype(bool), isl, err_msg=f"outage {c}")
+        nogen = oracle.redispatch(g.P, isl)[1]
+        expect = 0 if not isl.any() else (gp.ISLANDED_NO_GEN if nogen else gp.CONVERGED_ISLANDED)
+        assert res["status"][c] == expect, (c, res["status"][c], expect)
+    rng = np.random.default_rng(13)
+    sample = np.sort(rng.choice(g.m, 60, replace=False))
+    islanding = np.flatnonzero(res["island"].any(axis=1))
+    sample = np.union1d(sample, islanding[:4])
+    _check_against_direct(g, A, sample, {k: (v[sample] if v is not None else None) for k, v in res.items()})
 
 
 # --------------------------------------------------------- B'' context
