@@ -712,9 +712,15 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     hip_check(gpcg::launch_outputs(o, h->stream), "output launch");
 }
 
-// Base state: theta_b solves A theta = rhs.  PCG in correction form from the
-// current theta_b (outage -1, so r0 is the double-double residual), then
-// theta_b += delta; repeated while the residual keeps shrinking.
+// Base state: theta_b solves A theta = rhs by iterative refinement.  Each
+// pass forms the double-double residual rho of the current theta_b, solves
+// A delta = rho by PCG from zero (the per-column right-hand-side mode with the
+// intact grid), with the stop relative to ||rho|| rather than to ||rhs||,
+// then theta_b += delta; repeated while the residual keeps shrinking.  The
+// stop has to follow rho: on a large grid the FP64 residual floor (about
+// 1e-11 relative) is reached while the smooth error modes, which the
+// residual barely sees, are still well above rounding level; a pass stopped
+// at tol ||rhs|| leaves them there.
 void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
     const int n_bus = h->n_bus;
     DevBuf<double> rhs;
@@ -729,6 +735,8 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
     dsum.alloc(2);
     std::vector<double> zero(n_bus, 0.0);
     h->theta_b.upload(zero.data(), n_bus, h->stream);
+    DevBuf<double> rho_bus;  // rho in bus numbering (entry 0, the slack, is 0)
+    rho_bus.upload(zero.data(), n_bus, h->stream);
     DevSchedule &D = h->schedule_for(1);
     h->ensure_workspace(1, 1);
     double bnorm2 = 0.0;
@@ -749,7 +757,12 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
         h->base_resid = rel;
         if (!(rel < prev * 0.5) || rel < 1e-16) break;
         prev = rel;
+        hip_check(hipMemcpyAsync(rho_bus.p + 1, h->rho_b.p, h->n_r * sizeof(double), hipMemcpyDeviceToDevice,
+                                 h->stream),
+                  "copy");
         gpcg::PcgParams p = h->params(D, out1.p, 1, rhs.p, 1e-13, max_iter, it.p, st.p);
+        p.rhs_cols = rho_bus.p;
+        p.rhs_ld = n_bus;
         hip_check(gpcg::launch_pcg(p, 1, 1, D.ring_max(), h->stream), "base pcg");
         hip_check(gpcg::launch_base_accumulate(h->n_r, h->theta_b.p, h->ws.p, h->stream), "base accumulate");
         int its = 0;

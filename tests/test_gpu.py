@@ -38,9 +38,12 @@ def gp():
     return gp
 
 
-def _ctx(gp, g, block=64, kind=0, shunt=None, rhs=None):
+def _ctx(gp, g, block=64, kind=0, shunt=None, rhs=None, A=None):
     base = g.P if rhs is None else rhs
-    return gp.Context(g.n, g.br_from, g.br_to, g.x, base, block=block, kind=kind, shunt=shunt)
+    if A is not None:
+        A = A.tocsr()
+        A = gp.binding.Csr(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+    return gp.Context(g.n, g.br_from, g.br_to, g.x, base, block=block, kind=kind, shunt=shunt, A=A)
 
 
 def _run(gp, ctx, g, outages, rhs=None, tol=1e-12, max_iter=20000, plain=False):
@@ -222,15 +225,28 @@ def test_grid2k_all_outages_batched(gp, grids, block, tol):
 
 
 def test_grid10k_all_outages(gp, grids):
-    """Every outage of the 10,000-bus grid in one launch (block 16, the
-    recursive stop at 5e-11): island flags of all 13,500 outages bit-exact
-    against the brute-force component pass, every status and true residual
-    against the bar, angles and flows on a seeded sample of 60."""
+    """Every outage of the 10,000-bus grid in one launch (block 16): island
+    flags of all 13,500 outages bit-exact against the brute-force component
+    pass, every status and true residual against the bar, angles and flows
+    on a seeded sample of 60.
+
+    The recursive stop is 1e-12.  At this size the 5e-11 stop that meets the
+    residual bar does not meet the angle bar: outage 5132 then ends 2.2e-7
+    rad from the direct solution, in the oracle's own textbook PCG as on the
+    device.
+
+    Both sides solve the same matrix: the context is given the oracle's
+    assembled A (the C ABI takes the base matrix as an input).  At this size
+    the solution moves by about 1.9e-8 rad when the diagonal sums of A are
+    rounded in another order (a last-bit change in 1,415 entries), more than
+    the angle bar, so the library's own assembly (checked entry by entry
+    against the oracle's on the CPU) cannot be compared at 1e-8 here."""
     g = grids["grid10k"]
-    _, A = oracle.base_case(g)
-    ctx = _ctx(gp, g, block=16)
+    thb, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=16, A=A)
+    assert np.abs(ctx.base()[1] - thb).max() <= 1e-9
     outs = np.arange(g.m)
-    res = _run(gp, ctx, g, outs, tol=5e-11)
+    res = _run(gp, ctx, g, outs, tol=1e-12)
     assert res["resid"].max() <= RESID_TOL
     for c in outs:
         isl = oracle.island_of(g, int(c))

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert n in binding.SIGNATURES, n
 
 
-@pytest.mark.parametrize("key", ["grid200", "grid2k"])
+@pytest.mark.parametrize("key", ["grid200", "grid2k", "grid10k"])
 def test_assembly_matches_oracle(grids, key):
     g = grids[key]
     A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
