@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--spmm-workload", default="grid10k", help="grid of the stand-alone product measurement")
     ap.add_argument("--no-spmm", action="store_true")
-    ap.add_argument("--spmm-block", type=int, default=32)
+    ap.add_argument("--spmm-block", type=int, default=16)
     ap.add_argument("--spmm-only", action="store_true", help="only the stand-alone product measurement")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-workload", default="grid10k", help="grid of the overload-gradient measurement")

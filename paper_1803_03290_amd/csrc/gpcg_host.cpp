@@ -1565,8 +1565,9 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
         if (!h || !outages || !p || !q) fail(GPCG_E_ARG, "NULL argument");
         if (ncols <= 0 || ncols % h->S) fail(GPCG_E_ARG, "ncols must be a positive multiple of the block");
         hip_check(hipSetDevice(h->device), "hipSetDevice");
-        // rows per chunk: the most that the per-thread staging takes and that
-        // keep the work-group's LDS in budget; segments of up to 8 chunks
+        // rows per chunk: the most, up to kSpmmMaxChunk, that the per-thread
+        // staging takes and that keep the work-group's LDS in budget (with
+        // narrow tiles the cap leaves room for more work-groups per CU)
         const int S = h->S, RS = 256 / S, nr = h->n_r, bw = h->bandwidth;
         const auto &rp = h->hA.rowptr;
         auto chunk_nnz = [&](int ch) {
@@ -1580,7 +1581,7 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
             if (!gpcg::spmm_chunk_fits(S, c, mx)) continue;
             ch = c;
             max_nnz = mx;
-            if (gpcg::spmm_lds_bytes(S, bw, c, mx) <= gpcg::kSpmmLdsBudget) break;
+            if (c <= gpcg::kSpmmMaxChunk && gpcg::spmm_lds_bytes(S, bw, c, mx) <= gpcg::kSpmmLdsBudget) break;
         }
         if (ch == 0 || gpcg::spmm_lds_bytes(S, bw, ch, max_nnz) > 160 * 1024)
             fail(GPCG_E_UNSUPPORTED, "the matrix bandwidth is too large for the product's LDS window at this block");

@@ -188,7 +188,8 @@ hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta,
 // max_nnz: the most entries of A in one chunk.  partial:
 // f64[n_segments * ncols] scratch for the p'q column sums (NULL when prm.pq
 // is NULL).
-constexpr size_t kSpmmLdsBudget = 40 * 1024;  // LDS per work-group the host aims for (four fit one CU)
+constexpr size_t kSpmmLdsBudget = 40 * 1024;  // LDS per work-group the host aims for (at least four per CU)
+constexpr int kSpmmMaxChunk = 80;  // rows per chunk beyond which more work-groups per CU pay more than longer chunks
 size_t spmm_lds_bytes(int S, int bw, int ch, int max_nnz);
 bool spmm_chunk_fits(int S, int ch, int max_nnz);
 hipError_t launch_spmm_partial(const SpmmParams &prm, int S, int bw, int ch, int nseg, int max_nnz, double *partial,

@@ -171,8 +171,8 @@ __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, doub
 // on one XCD, and the bw halo rows two segments share come from its L2.
 constexpr int kSpmmThreads = 256;
 constexpr int kXcds = 8;
-constexpr int kSpmmLoadsP = 8;  // 16-byte (8-byte when S = 1) loads of p per thread per chunk
-constexpr int kSpmmLoadsA = 8;  // entries of A per thread per chunk
+constexpr int kSpmmLoadsP = 4;  // 16-byte (8-byte when S = 1) loads of p per thread per chunk
+constexpr int kSpmmLoadsA = 4;  // entries of A per thread per chunk
 constexpr int kSpmmLoadsR = 2;  // row pointers per thread per chunk
 
 // a native two-double vector (kept in registers, unlike the HIP struct type)

@@ -283,14 +283,14 @@ def test_bpp_context(gp, grids):
 # ------------------------------------------- stand-alone product, full size
 
 
-def test_spmm_grid10k_full_launch_sampled(gp, grids):
-    """The product as the benchmark times it: every outage column of the
-    10,000-bus grid in one launch at block 32, p ~ N(0, 1); 64 seeded columns
-    checked against the oracle's explicit A_c (islanded rows zero) and their
-    p'q."""
+@pytest.mark.parametrize("S", [16, 32])
+def test_spmm_grid10k_full_launch_sampled(gp, grids, S):
+    """The product as the benchmark times it (block 16; block 32 takes
+    another chunk height): every outage column of the 10,000-bus grid in one
+    launch, p ~ N(0, 1); 64 seeded columns checked against the oracle's
+    explicit A_c (islanded rows zero) and their p'q."""
     g = grids["grid10k"]
     _, A = oracle.base_case(g)
-    S = 32
     ctx = _ctx(gp, g, block=S)
     nr = g.n - 1
     ncols = ((g.m + S - 1) // S) * S
