@@ -304,7 +304,7 @@ struct CsrH {
 struct HostProg {
     int steps = 0, ring = 1;
     std::vector<int32_t> rec;  // 4 per (step, slot)
-    std::vector<int32_t> ent;  // 3 per (step, entry, slot)
+    std::vector<int32_t> ent;  // 3 per (step, entry, slot), chunk-major (see gpcg::Program)
     std::vector<double> dinv;  // per (step, slot), backward only
 };
 
@@ -384,14 +384,6 @@ int ring_needed(const Steps &st, const CsrH &T, bool tri, int max_ring) {
     return -1;
 }
 
-void put_entry(std::vector<int32_t> &ent, double v, int lds) {
-    int32_t w[2];
-    std::memcpy(w, &v, sizeof v);
-    ent.push_back(w[0]);
-    ent.push_back(w[1]);
-    ent.push_back(lds);
-}
-
 // Pack an expanded step list for the kernel (see gpcg::Program).
 HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, bool tri,
               const std::vector<double> *invdiag, const std::vector<int32_t> &prerow) {
@@ -418,16 +410,28 @@ HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, boo
             }
             if (invdiag) H.dinv.push_back(sl.row >= 0 ? (*invdiag)[sl.row] : 0.0);
         }
-        for (int j = 0; j < K; ++j)
-            for (int k = 0; k < R; ++k) {
-                const Slot &sl = step[k];
+        // per slot: K values (two to a 16-byte chunk), then K ring offsets
+        // (four to a chunk); stored chunk-major, chunk c of slot k at
+        // ((step, c), k)
+        std::vector<int32_t> w((size_t)R * 3 * K);
+        for (int k = 0; k < R; ++k) {
+            const Slot &sl = step[k];
+            int32_t *vals = &w[(size_t)k * 3 * K], *offs = vals + 2 * K;
+            for (int j = 0; j < K; ++j) {
+                double v = 0.0;
+                int lds = zero;
                 if (sl.src >= 0 && sl.seg_begin + j < sl.seg_end) {
                     const int e = T.rowptr[sl.src] + sl.seg_begin + j;
-                    put_entry(H.ent, T.val[e], (T.col[e] & (ring - 1)) * S * 8);
-                } else {
-                    put_entry(H.ent, 0.0, zero);
+                    v = T.val[e];
+                    lds = (T.col[e] & (ring - 1)) * S * 8;
                 }
+                std::memcpy(vals + 2 * j, &v, sizeof v);
+                offs[j] = lds;
             }
+        }
+        for (int c = 0; c < 3 * K / 4; ++c)
+            for (int k = 0; k < R; ++k)
+                for (int t = 0; t < 4; ++t) H.ent.push_back(w[(size_t)k * 3 * K + c * 4 + t]);
     }
     return H;
 }
@@ -479,7 +483,7 @@ struct DevProgram {
     gpcg::Program view() const {
         gpcg::Program g{};
         g.rec = (const int4 *)rec.p;
-        g.ent = (const int3 *)ent.p;
+        g.ent = (const int4 *)ent.p;
         g.dinv = dinv.p;
         g.steps = steps;
         g.ring = ring;

@@ -41,12 +41,14 @@ constexpr int kEntProd = 8;
 //          continuation segment of the product);
 //     aux: triangular solves: 1 for a continuation segment, else 0 (-1 idle);
 //          product: the look-ahead row whose direction is updated, or -1.
-//   ent[(s * K + j) * R + rs] = {value lo, value hi, LDS byte offset of the
-//     column's ring slot for column 0};
+//   entries of slot rs of step s, in 3K/4 sixteen-byte chunks
+//     ent[(s * 3K/4 + c) * R + rs]: chunks c < K/2 hold the values of
+//     entries 2c and 2c + 1 (doubles), chunks K/2 + c' the LDS byte offsets
+//     of the ring slots (for column 0) of entries 4c' .. 4c' + 3;
 //   dinv[s * R + rs] = 1 / U_ii (backward solve only).
 struct Program {
     const int4 *rec;
-    const int3 *ent;
+    const int4 *ent;
     const double *dinv;
     int steps, ring;
 };

@@ -64,18 +64,33 @@ __device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
     *(double *)((char *)ring + byte_off) = v;
 }
 
+// A step's K entry records for this lane's slot, in 3 K / 4 sixteen-byte
+// chunks: K / 2 chunks of two values each, then K / 4 chunks of four ring
+// byte offsets.  Chunk c of every slot of a step is stored contiguously, so
+// each chunk is one coalesced 16-byte load into an aligned register group.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
 template <int K>
 struct Ents {
-    int3 e[K];
+    static_assert(K % 4 == 0, "entry records come in 16-byte chunks");
+    dvec2 v[K / 2];
+    int4 o[K / 4];
+    __device__ __forceinline__ double val(int j) const { return v[j / 2][j % 2]; }
+    __device__ __forceinline__ int off(int j) const {
+        const int4 &w = o[j / 4];
+        return (j % 4 == 0) ? w.x : (j % 4 == 1) ? w.y : (j % 4 == 2) ? w.z : w.w;
+    }
 };
 
 template <int S, int K>
 __device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, int rs) {
-    constexpr int R = kWave / S;
+    constexpr int R = kWave / S, C = 3 * K / 4;
     const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
-    const int3 *base = g.ent + ((size_t)ss * K) * R + rs;
+    const int4 *base = g.ent + ((size_t)ss * C) * R + rs;
 #pragma unroll
-    for (int j = 0; j < K; ++j) E.e[j] = base[j * R];
+    for (int c = 0; c < K / 2; ++c) E.v[c] = *(const dvec2 *)(base + c * R);
+#pragma unroll
+    for (int c = 0; c < K / 4; ++c) E.o[c] = base[(K / 2 + c) * R];
 }
 
 // A step's ring values and entry values, gathered before the step's refill
@@ -89,8 +104,8 @@ template <int K>
 __device__ __forceinline__ void gather(Gath<K> &G, const Ents<K> &E, const double *ring, int lane_off) {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        G.r[j] = ring_at(ring, E.e[j].z + lane_off);
-        G.v[j] = __hiloint2double(E.e[j].y, E.e[j].x);
+        G.r[j] = ring_at(ring, E.off(j) + lane_off);
+        G.v[j] = E.val(j);
     }
 }
 
@@ -146,7 +161,7 @@ __device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
 template <int K>
 __device__ __forceinline__ void ring_addr(int (&a)[K], const Ents<K> &E, int lane_off) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) a[j] = E.e[j].z + lane_off;
+    for (int j = 0; j < K; ++j) a[j] = E.off(j) + lane_off;
 }
 
 template <int K>
@@ -161,8 +176,7 @@ __device__ __forceinline__ double tree_dot(const double (&r)[K], const Ents<K> &
     double acc[K / 2];
 #pragma unroll
     for (int j = 0; j < K / 2; ++j)
-        acc[j] = __builtin_fma(__hiloint2double(E.e[2 * j + 1].y, E.e[2 * j + 1].x), r[2 * j + 1],
-                               __hiloint2double(E.e[2 * j].y, E.e[2 * j].x) * r[2 * j]);
+        acc[j] = __builtin_fma(E.val(2 * j + 1), r[2 * j + 1], E.val(2 * j) * r[2 * j]);
 #pragma unroll
     for (int w = 1; w < K / 2; w <<= 1)
 #pragma unroll
@@ -211,6 +225,7 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
         for (int d = 0; d < H; ++d) {
             const int s = s0 + d;
             const int4 h = hq[d];
+            asm volatile("" ::"v"(h.z));  // unused here; keeps the record one 16-byte load
             // A
             const double dot = tree_dot(G, eq[d % E]);
             const double y = rc - dot;
