@@ -612,7 +612,7 @@ struct gpcg_context {
 
     void ensure_workspace(int n_out, int S_) {
         const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
-        const size_t need = tiles * gpcg::kVectors * (size_t)(n_r + 1) * S_;
+        const size_t need = tiles * gpcg::kVectors * gpcg::vec_stride(n_r, S_);
         if (ws.n < need) ws.alloc(need);
         if (gfac.n < (size_t)std::max(n_out, 1)) gfac.alloc(std::max(n_out, 1));
     }
@@ -897,7 +897,7 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
         h->schedule_for(S);
         G->sched = (S == 1) ? h->sched_plain : h->sched_batched;
         b->ring = std::max(b->ring, G->sched->ring_max());
-        G->ws.alloc(std::max<size_t>(1, (size_t)G->tiles * gpcg::kVectors * (size_t)(h->n_r + 1) * S));
+        G->ws.alloc(std::max<size_t>(1, (size_t)G->tiles * gpcg::kVectors * gpcg::vec_stride(h->n_r, S)));
         G->rho_b.alloc(h->n_r);
         G->gfac.alloc(std::max(G->n_out, 1));
         gpcg::PcgParams p = h->params(*G->sched, G->outages, G->n_out, G->rhs, tol, max_iter, G->iters_out,

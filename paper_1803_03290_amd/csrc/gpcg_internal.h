@@ -10,6 +10,9 @@ namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
 constexpr int kVectors = 5;   // per tile: delta, r, p, q, y/z, each (n_r + 1) x S
+// doubles per vector of a tile: (n_r + 1) rows x S columns, rounded up to
+// even so that every vector, and every {delta, p} pair, is 16-byte aligned
+constexpr size_t vec_stride(int n_r, int S) { return ((size_t)(n_r + 1) * S + 1) / 2 * 2; }
 constexpr int kLdsBudget = 80 * 1024;  // bytes of LDS ring per wavefront (two waves fit one CU)
 
 enum Status : int32_t {
@@ -83,7 +86,7 @@ struct PcgParams {
     int tile0;  // first tile of this launch (plain mode launches one tile at a time)
     double tol2;
     int max_iter;
-    double *ws;  // tiles x kVectors x (n_r + 1) rows x S
+    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, then r, q, y / z
     int32_t *iters_out, *status_out;
     double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
 };

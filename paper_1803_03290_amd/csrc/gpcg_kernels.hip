@@ -51,7 +51,9 @@ __global__ void theta_out_kernel(OutParams p) {
     if (k > 0 && !in && !bad) {
         const int j = p.pos ? p.pos[s] : s;
         const int tile = j / p.S, sc = j % p.S;
-        th = (p.add_base ? p.theta_b[k] : 0.0) + p.ws[((size_t)tile * kVectors * (p.n_r + 1) + (k - 1)) * p.S + sc];
+        // delta is the first of the pair {delta, p} of (row k - 1, column sc)
+        th = (p.add_base ? p.theta_b[k] : 0.0) +
+             p.ws[(size_t)tile * kVectors * vec_stride(p.n_r, p.S) + ((size_t)(k - 1) * p.S + sc) * 2];
     }
     p.x_out[(size_t)s * p.n_bus + k] = th;
     if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
@@ -139,10 +141,11 @@ __global__ void base_residual_kernel(int n_r, const int32_t *__restrict__ rowptr
     rho[i] = h + l;
 }
 
-// theta_b += delta, delta read from tile 0 of a one-column (S = 1) workspace
-__global__ void base_accumulate_kernel(int n_r, double *theta_b, const double *delta) {
+// theta_b += delta, delta read from the {delta, p} pairs of tile 0 of a
+// one-column (S = 1) workspace
+__global__ void base_accumulate_kernel(int n_r, double *theta_b, const double *delta_p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_r) theta_b[i + 1] += delta[i];
+    if (i < n_r) theta_b[i + 1] += delta_p[2 * i];
 }
 
 __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, double *out) {

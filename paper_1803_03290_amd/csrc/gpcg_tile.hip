@@ -4,11 +4,14 @@
 // carries it through the whole preconditioned CG of Section III.A.  Its 64
 // lanes are R x S with R = 64 / S: lane = rs * S + sc treats scenario column
 // sc and row slot rs.  Per tile the workspace holds five vectors: delta (the
-// change of state from the base case), r, p, q = A_c p, and y / z (the
-// forward-solve result, overwritten by the backward-solve result), stored
-// one after the other, each (n_r + 1) x S row-major (row n_r is scratch), so
-// a wave touching a row of one vector reads S contiguous doubles and every
-// matrix entry it reads is shared by the S columns.
+// change of state from the base case), p, r, q = A_c p, and y / z (the
+// forward-solve result, overwritten by the backward-solve result), each
+// (n_r + 1) x S row-major (row n_r is scratch).  delta and p, which only the
+// product sweep touches and always together, are interleaved as pairs
+// {delta, p} per (row, column) in the first two vector slots; r, q and y / z
+// follow one after the other.  A wave touching a row of a vector reads S
+// contiguous doubles (pairs), and every matrix entry it reads is shared by
+// the S columns.
 //
 // The outage of branch c = (f, t) is applied as a rank-1 correction of the
 // shared base matrix: A_c = A - b_c u u^T with u = e_f - e_t (Section IV.B:
@@ -39,11 +42,12 @@ namespace {
 // (row n_r) and the ring's trash row, and padding entries are real zero
 // entries in memory.
 //
-// A tile stores its five vectors one after the other, each row-major with
-// S columns: a wave's access to one vector row is S contiguous doubles, and
-// every sweep reads only the vectors it needs.  Vector bases are wave-uniform
-// (scalar registers); a step computes one 32-bit offset for all of them.
-enum : int { VX = 0, VR = 1, VP = 2, VQ = 3, VY = 4 };
+// A tile stores the pairs {delta, p} and then r, q, y / z, each row-major
+// with S columns: a wave's access to one vector row is S contiguous doubles
+// (or pairs), and every sweep reads only the vectors it needs.  Vector bases
+// are wave-uniform (scalar registers); a step computes one 32-bit offset for
+// all of them (twice it for the pairs).
+enum : int { VR = 2, VQ = 3, VY = 4 };
 constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
 constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
 
@@ -118,8 +122,10 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
     return acc;
 }
 
-// A tile's five vectors, each (n_r + 1) rows x S columns (row n_r is scratch).
+// A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
+// the {delta, p} pairs at xp, r, q, y / z at v[VR], v[VQ], v[VY].
 struct Tile {
+    double *xp;
     double *v[kVectors];
     int nr;
 };
@@ -137,6 +143,18 @@ __device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
 
 __device__ __forceinline__ void vput(const Tile &T, int v, unsigned off, double x) {
     *(double *)((char *)T.v[v] + off) = x;
+}
+
+// the pair {delta, p} at the element offset off of the other vectors
+__device__ __forceinline__ dvec2 xp_get(const Tile &T, unsigned off) {
+    return *(const dvec2 *)((const char *)T.xp + 2 * off);
+}
+
+__device__ __forceinline__ void xp_put(const Tile &T, unsigned off, double x, double pv) {
+    dvec2 w;
+    w.x = x;
+    w.y = pv;
+    *(dvec2 *)((char *)T.xp + 2 * off) = w;
 }
 
 // Programs end with kPadSteps idle steps, so reading past the last real step
@@ -334,8 +352,9 @@ template <int S>
 __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
     const unsigned o = row_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
     v.z = vget(T, VY, o);
-    v.p = vget(T, VP, o);
-    v.x = vget(T, VX, o);
+    const dvec2 xp = xp_get(T, o);
+    v.x = xp.x;
+    v.p = xp.y;
 }
 
 template <int S, int D>
@@ -379,8 +398,7 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
             load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
             hq[d] = load_head<S>(g, s + H, rs);
             {
-                vput(T, VX, lo_, v.x + alpha * v.p);
-                vput(T, VP, lo_, pn);
+                xp_put(T, lo_, v.x + alpha * v.p, pn);
                 const double dot = gdot(G);
                 double qv = carry + dot;
                 carry = (h.z == -2) ? carry + dot : 0.0;
@@ -403,7 +421,8 @@ __device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, doub
     constexpr int R = kWave / S;
     for (int i = rs; i < T.nr; i += R) {
         const unsigned o = row_off<S>(T, i, sc);
-        vput(T, VX, o, vget(T, VX, o) + alpha * vget(T, VP, o));
+        const dvec2 xp = xp_get(T, o);
+        xp_put(T, o, xp.x + alpha * xp.y, xp.y);
     }
 }
 
@@ -420,7 +439,8 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
     const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
     const int nr = p.n_r;
     Tile T;
-    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * (nr + 1) * S;
+    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * vec_stride(nr, S);
+    T.xp = T.v[0];
     T.nr = nr;
 
     // ---- per-column outage data -------------------------------------------
@@ -452,9 +472,8 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             const double r0 = (valid && !in_interval(p.pre_row[i], lo, hi)) ? b[i] : 0.0;
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
-            vput(T, VX, o, 0.0);
+            xp_put(T, o, 0.0, 0.0);
             vput(T, VR, o, r0);
-            vput(T, VP, o, 0.0);
             vput(T, VQ, o, 0.0);
         }
         bb = rr;
@@ -495,15 +514,17 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             }
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
-            vput(T, VX, o, 0.0);
+            xp_put(T, o, 0.0, 0.0);
             vput(T, VR, o, r0);
-            vput(T, VP, o, 0.0);
             vput(T, VQ, o, 0.0);
         }
     }
     if (rs == 0) {
         const unsigned o = row_off<S>(T, nr, sc);
-        for (int v = 0; v < kVectors; ++v) vput(T, v, o, 0.0);
+        xp_put(T, o, 0.0, 0.0);
+        vput(T, VR, o, 0.0);
+        vput(T, VQ, o, 0.0);
+        vput(T, VY, o, 0.0);
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
