@@ -86,7 +86,7 @@ struct PcgParams {
     int tile0;  // first tile of this launch (plain mode launches one tile at a time)
     double tol2;
     int max_iter;
-    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, then r, q, y / z
+    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, pairs {r, y / z}, q
     int32_t *iters_out, *status_out;
     double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
 };

@@ -8,8 +8,9 @@
 // forward-solve result, overwritten by the backward-solve result), each
 // (n_r + 1) x S row-major (row n_r is scratch).  delta and p, which only the
 // product sweep touches and always together, are interleaved as pairs
-// {delta, p} per (row, column) in the first two vector slots; r, q and y / z
-// follow one after the other.  A wave touching a row of a vector reads S
+// {delta, p} per (row, column) in the first two vector slots; r and y / z,
+// which the forward sweep stores together and the backward sweep loads
+// together, as pairs {r, y / z} in the next two; q follows.  A wave touching a row of a vector reads S
 // contiguous doubles (pairs), and every matrix entry it reads is shared by
 // the S columns.
 //
@@ -42,12 +43,12 @@ namespace {
 // (row n_r) and the ring's trash row, and padding entries are real zero
 // entries in memory.
 //
-// A tile stores the pairs {delta, p} and then r, q, y / z, each row-major
+// A tile stores the pairs {delta, p}, the pairs {r, y / z} and q, each row-major
 // with S columns: a wave's access to one vector row is S contiguous doubles
 // (or pairs), and every sweep reads only the vectors it needs.  Vector bases
 // are wave-uniform (scalar registers); a step computes one 32-bit offset for
 // all of them (twice it for the pairs).
-enum : int { VR = 2, VQ = 3, VY = 4 };
+enum : int { VQ = 4 };
 constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
 constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
 
@@ -123,9 +124,9 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
 }
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
-// the {delta, p} pairs at xp, r, q, y / z at v[VR], v[VQ], v[VY].
+// the {delta, p} pairs at xp, the {r, y / z} pairs at ry, q at v[VQ].
 struct Tile {
-    double *xp;
+    double *xp, *ry;
     double *v[kVectors];
     int nr;
 };
@@ -155,6 +156,30 @@ __device__ __forceinline__ void xp_put(const Tile &T, unsigned off, double x, do
     w.x = x;
     w.y = pv;
     *(dvec2 *)((char *)T.xp + 2 * off) = w;
+}
+
+// the pair {r, y / z}, and its halves, at the element offset off
+__device__ __forceinline__ dvec2 ry_get(const Tile &T, unsigned off) {
+    return *(const dvec2 *)((const char *)T.ry + 2 * off);
+}
+
+__device__ __forceinline__ void ry_put(const Tile &T, unsigned off, double r, double y) {
+    dvec2 w;
+    w.x = r;
+    w.y = y;
+    *(dvec2 *)((char *)T.ry + 2 * off) = w;
+}
+
+__device__ __forceinline__ double r_get(const Tile &T, unsigned off) {
+    return *(const double *)((const char *)T.ry + 2 * off);
+}
+
+__device__ __forceinline__ double y_get(const Tile &T, unsigned off) {
+    return *(const double *)((const char *)T.ry + 2 * off + 8);
+}
+
+__device__ __forceinline__ void y_put(const Tile &T, unsigned off, double y) {
+    *(double *)((char *)T.ry + 2 * off + 8) = y;
 }
 
 // Programs end with kPadSteps idle steps, so reading past the last real step
@@ -210,7 +235,7 @@ struct FwdVec {
 template <int S>
 __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
     const unsigned o = row_off<S>(T, h.x, sc);
-    v.r = vget(T, VR, o);
+    v.r = r_get(T, o);
     v.q = vget(T, VQ, o);
 }
 
@@ -254,8 +279,7 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
             // B
             {
                 const unsigned o = row_off<S>(T, h.x, sc);
-                vput(T, VR, o, r);
-                vput(T, VY, o, y);
+                ry_put(T, o, r, y);
                 rr += (h.x >= 0) ? r * r : 0.0;
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
@@ -281,8 +305,9 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program 
                                         int sc) {
     constexpr int R = kWave / S;
     const unsigned o = row_off<S>(T, h.x, sc);
-    v.y = vget(T, VY, o);
-    v.r = vget(T, VR, o);
+    const dvec2 ry = ry_get(T, o);
+    v.y = ry.y;
+    v.r = ry.x;
     v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
 }
 
@@ -324,7 +349,7 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
             // B
             {
                 const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
-                vput(T, VY, row_off<S>(T, h.x, sc), zm);
+                y_put(T, row_off<S>(T, h.x, sc), zm);
                 rz += (h.x >= 0) ? r * zm : 0.0;
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 const BwdVec v = vq[(d + 1) % D];
@@ -351,7 +376,7 @@ struct ProdVec {
 template <int S>
 __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
     const unsigned o = row_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
-    v.z = vget(T, VY, o);
+    v.z = y_get(T, o);
     const dvec2 xp = xp_get(T, o);
     v.x = xp.x;
     v.p = xp.y;
@@ -441,6 +466,7 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
     Tile T;
     for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * vec_stride(nr, S);
     T.xp = T.v[0];
+    T.ry = T.v[2];
     T.nr = nr;
 
     // ---- per-column outage data -------------------------------------------
@@ -473,7 +499,7 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
             xp_put(T, o, 0.0, 0.0);
-            vput(T, VR, o, r0);
+            ry_put(T, o, r0, 0.0);
             vput(T, VQ, o, 0.0);
         }
         bb = rr;
@@ -515,16 +541,15 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
             xp_put(T, o, 0.0, 0.0);
-            vput(T, VR, o, r0);
+            ry_put(T, o, r0, 0.0);
             vput(T, VQ, o, 0.0);
         }
     }
     if (rs == 0) {
         const unsigned o = row_off<S>(T, nr, sc);
         xp_put(T, o, 0.0, 0.0);
-        vput(T, VR, o, 0.0);
+        ry_put(T, o, 0.0, 0.0);
         vput(T, VQ, o, 0.0);
-        vput(T, VY, o, 0.0);
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
