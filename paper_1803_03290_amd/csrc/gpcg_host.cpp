@@ -393,10 +393,11 @@ HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, boo
     const int zero = ring * S * 8, trash = (ring + 1) * S * 8;
     Steps all = st;  // plus idle steps that the kernel's prefetch may read past the end
     all.insert(all.end(), gpcg::kPadSteps, std::vector<Slot>(R));
+    const int nr = (int)T.rowptr.size() - 1;  // idle slots name the scratch row n_r
     for (const auto &step : all) {
         for (int k = 0; k < R; ++k) {
             const Slot &sl = step[k];
-            H.rec.push_back(sl.row);
+            H.rec.push_back(sl.row >= 0 ? sl.row : nr);
             if (sl.row >= 0)
                 H.rec.push_back((sl.row & (ring - 1)) * S * 8);
             else
@@ -406,7 +407,7 @@ HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, boo
                 H.rec.push_back(sl.cont ? 1 : (sl.row >= 0 ? 0 : -1));
             } else {
                 H.rec.push_back(sl.cont ? -2 : (sl.row >= 0 ? prerow[sl.row] : -1));
-                H.rec.push_back(sl.la);
+                H.rec.push_back(sl.la >= 0 ? sl.la : nr);
             }
             if (invdiag) H.dinv.push_back(sl.row >= 0 ? (*invdiag)[sl.row] : 0.0);
         }

@@ -37,13 +37,14 @@ constexpr int kEntProd = 8;
 // slot with a fixed number K of packed matrix entries (padding entries carry
 // value 0 and point at the ring's zero row).
 //   rec[s * R + rs] = {row, own, pre, aux}:
-//     row: the row finished in this slot (-1: idle or continuation segment);
+//     row: the row finished in this slot (n_r, the scratch row, when the
+//          slot is idle or holds a continuation segment);
 //     own: LDS byte offset of that row's ring slot for column 0 (the trash
 //          row when row is -1; the zero row for idle product slots);
 //     pre: pre-order number of the row's bus (-1 when none; -2 marks a
 //          continuation segment of the product);
 //     aux: triangular solves: 1 for a continuation segment, else 0 (-1 idle);
-//          product: the look-ahead row whose direction is updated, or -1.
+//          product: the look-ahead row whose direction is updated, or n_r.
 //   entries of slot rs of step s, in 3K/4 sixteen-byte chunks
 //     ent[(s * 3K/4 + c) * R + rs]: chunks c < K/2 hold the values of
 //     entries 2c and 2c + 1 (doubles), chunks K/2 + c' the LDS byte offsets

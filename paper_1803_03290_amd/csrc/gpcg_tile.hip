@@ -131,11 +131,11 @@ struct Tile {
     int nr;
 };
 
-// byte offset of (row, column sc) inside any vector of a tile; idle slots
-// (row -1) go to the scratch row
+// byte offset of (row, column sc) inside any vector of a tile (idle slots
+// name the scratch row n_r)
 template <int S>
 __device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
-    return ((unsigned)(row >= 0 ? row : T.nr) * S + sc) * 8u;
+    return ((unsigned)row * S + sc) * 8u;
 }
 
 __device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
@@ -280,7 +280,7 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
             {
                 const unsigned o = row_off<S>(T, h.x, sc);
                 ry_put(T, o, r, y);
-                rr += (h.x >= 0) ? r * r : 0.0;
+                rr += (h.x < T.nr) ? r * r : 0.0;
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
                 r = v.r - alpha * v.q;
@@ -350,7 +350,7 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
             {
                 const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
                 y_put(T, row_off<S>(T, h.x, sc), zm);
-                rz += (h.x >= 0) ? r * zm : 0.0;
+                rz += (h.x < T.nr) ? r * zm : 0.0;
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 const BwdVec v = vq[(d + 1) % D];
                 yc = v.y - carry;
@@ -414,7 +414,7 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
             // ring write must precede this step's reads)
             const unsigned lo_ = row_off<S>(T, h.w, sc);
             const double pn = done ? v.p : v.z + beta * v.p;
-            ring_put(ring, ((h.w >= 0) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
+            ring_put(ring, ((h.w < T.nr) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
             Gath<kEntProd> G;
             gather(G, eq[d % E], ring, lane_off);
             const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
@@ -431,7 +431,7 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
                 qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
                 if (in_interval(h.z, lo, hi)) qv = 0.0;
                 vput(T, VQ, row_off<S>(T, h.x, sc), qv);
-                pq += (h.x >= 0) ? pown * qv : 0.0;
+                pq += (h.x < T.nr) ? pown * qv : 0.0;
             }
             __builtin_amdgcn_sched_barrier(0);
         }
