@@ -87,15 +87,22 @@ struct Ents {
     }
 };
 
+// Loads of a step's records through a slot pointer: the step's chunk 0 of
+// slot rs (program base + (step * 3K/4) * R + rs), formed once per unrolled
+// iteration so that every step's loads use constant offsets from it.
 template <int S, int K>
-__device__ __forceinline__ void load_ents(Ents<K> &E, const Program &g, int s, int rs) {
-    constexpr int R = kWave / S, C = 3 * K / 4;
-    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
-    const int4 *base = g.ent + ((size_t)ss * C) * R + rs;
+__device__ __forceinline__ const int4 *ent_slot(const Program &g, int s, int rs) {
+    constexpr int R = kWave / S;
+    return g.ent + (size_t)s * (3 * K / 4) * R + rs;
+}
+
+template <int S, int K>
+__device__ __forceinline__ void load_ents(Ents<K> &E, const int4 *p) {
+    constexpr int R = kWave / S;
 #pragma unroll
-    for (int c = 0; c < K / 2; ++c) E.v[c] = *(const dvec2 *)(base + c * R);
+    for (int c = 0; c < K / 2; ++c) E.v[c] = *(const dvec2 *)(p + c * R);
 #pragma unroll
-    for (int c = 0; c < K / 4; ++c) E.o[c] = base[(K / 2 + c) * R];
+    for (int c = 0; c < K / 4; ++c) E.o[c] = p[(K / 2 + c) * R];
 }
 
 // A step's ring values and entry values, gathered before the step's refill
@@ -182,15 +189,14 @@ __device__ __forceinline__ void y_put(const Tile &T, unsigned off, double y) {
     *(double *)((char *)T.ry + 2 * off + 8) = y;
 }
 
-// Programs end with kPadSteps idle steps, so reading past the last real step
-// only needs a clamp (no branch that would wait for the load).
+// Programs end with kPadSteps idle steps, more than the deepest prefetch
+// reads past the last real step, so the loads need neither a clamp nor a
+// branch that would wait for them.
 template <int S>
-__device__ __forceinline__ int4 load_head(const Program &g, int s, int rs) {
+__device__ __forceinline__ const int4 *head_slot(const Program &g, int s, int rs) {
     constexpr int R = kWave / S;
-    const int ss = opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1);
-    return g.rec[ss * R + rs];
+    return g.rec + (size_t)s * R + rs;
 }
-
 // ---- triangular sweeps -----------------------------------------------------
 // Consecutive steps of a triangular solve may depend on each other through
 // the ring, so a step is split in two.  Part A is the chain: finish the ring
@@ -244,18 +250,22 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
                                             double alpha) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
+    static_assert(2 * H - 1 <= kPadSteps, "prefetch past the last step must stay in the padding");
+    constexpr int R = kWave / S, KE = K, C = 3 * K / 4;
+    const int z0 = opaque(0);
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rr = 0.0, carry = 0.0;
     int4 hq[H];
     FwdVec vq[D];
     Ents<K> eq[E];
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
 #pragma unroll
     for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -264,9 +274,11 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
     double rc = r;                         // ... minus its carry
     fwd_vec<S>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);  // step base: every address below is a constant offset from it
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *eb = ent_slot<S, KE>(g, sb, rs);
 #pragma unroll
         for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
             const int4 h = hq[d];
             asm volatile("" ::"v"(h.z));  // unused here; keeps the record one 16-byte load
             // A
@@ -286,9 +298,9 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
                 r = v.r - alpha * v.q;
                 rc = r - carry;
             }
-            load_ents<S, K>(eq[d % E], g, s + E, rs);
+            load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
             fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = load_head<S>(g, s + H, rs);
+            hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -301,43 +313,46 @@ struct BwdVec {
 };
 
 template <int S>
-__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Program &g, int s, int rs, const Tile &T,
-                                        int sc) {
-    constexpr int R = kWave / S;
+__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const double *dinv, const Tile &T, int sc) {
     const unsigned o = row_off<S>(T, h.x, sc);
     const dvec2 ry = ry_get(T, o);
     v.y = ry.y;
     v.r = ry.x;
-    v.dinv = g.dinv[opaque(s < g.steps + kPadSteps - 1 ? s : g.steps + kPadSteps - 1) * R + rs];
+    v.dinv = *dinv;
 }
-
 template <int S, int D>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
                                             int hi) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
+    static_assert(2 * H - 1 <= kPadSteps, "prefetch past the last step must stay in the padding");
+    constexpr int R = kWave / S, KE = K, C = 3 * K / 4;
+    const int z0 = opaque(0);
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
     double rz = 0.0, carry = 0.0;
     int4 hq[H];
     BwdVec vq[D];
     Ents<K> eq[E];
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
 #pragma unroll
-    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g, d, rs, T, sc);
+    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g.dinv + (size_t)z0 * R + rs + d * R, T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], g, d, rs);
+    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
     ring_read(G, ga, ring);
     double yc = vq[0].y, dv = vq[0].dinv, r = vq[0].r;  // step 0's row
-    bwd_vec<S>(vq[0], hq[D], g, D, rs, T, sc);
+    bwd_vec<S>(vq[0], hq[D], g.dinv + (size_t)z0 * R + rs + D * R, T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);  // step base: every address below is a constant offset from it
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *eb = ent_slot<S, KE>(g, sb, rs);
 #pragma unroll
         for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
             const int4 h = hq[d];
             // A
             const double dot = tree_dot(G, eq[d % E]);
@@ -357,9 +372,9 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
                 dv = v.dinv;
                 r = v.r;
             }
-            load_ents<S, K>(eq[d % E], g, s + E, rs);
-            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g, s + 1 + D, rs, T, sc);
-            hq[d] = load_head<S>(g, s + H, rs);
+            load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
+            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g.dinv + (size_t)sb * R + rs + (d + 1 + D) * R, T, sc);
+            hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -387,6 +402,9 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
                                              double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
                                              double bc) {
     constexpr int H = 2 * D, E = kEntAheadProd;
+    static_assert(2 * H - 1 <= kPadSteps && E <= H, "prefetch past the last step must stay in the padding");
+    constexpr int R = kWave / S, KE = kEntProd, C = 3 * kEntProd / 4;
+    const int z0 = opaque(0);
     const int lane_off = sc * 8;
     const int wm = g.ring - 1;
     const int zero = g.ring * S * 8;
@@ -398,16 +416,19 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
     int4 hq[H];
     ProdVec vq[D];
     Ents<kEntProd> eq[E];
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = load_head<S>(g, d, rs);
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
 #pragma unroll
     for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], g, d, rs);
+    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], ent_slot<S, kEntProd>(g, z0, rs) + d * C * R);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);  // step base: every address below is a constant offset from it
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *eb = ent_slot<S, KE>(g, sb, rs);
 #pragma unroll
         for (int d = 0; d < H; ++d) {
-            const int s = s0 + d;
             const int4 h = hq[d];
             const ProdVec v = vq[d % D];
             // look-ahead row: pending solution update and new direction (its
@@ -420,8 +441,8 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
             const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
             const double pown = ring_at(ring, h.y + lane_off);
             prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
-            load_ents<S, kEntProd>(eq[d % E], g, s + E, rs);
-            hq[d] = load_head<S>(g, s + H, rs);
+            load_ents<S, kEntProd>(eq[d % E], eb + (d + E) * C * R);
+            hq[d] = hb[(d + H) * R];
             {
                 xp_put(T, lo_, v.x + alpha * v.p, pn);
                 const double dot = gdot(G);
