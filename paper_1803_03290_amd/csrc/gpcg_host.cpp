@@ -305,7 +305,6 @@ struct HostProg {
     int steps = 0, ring = 1;
     std::vector<int32_t> rec;  // 4 per (step, slot)
     std::vector<int32_t> ent;  // 3 per (step, entry, slot), chunk-major (see gpcg::Program)
-    std::vector<double> dinv;  // per (step, slot), backward only
 };
 
 // One slot of a step before packing.
@@ -397,19 +396,29 @@ HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, boo
     for (const auto &step : all) {
         for (int k = 0; k < R; ++k) {
             const Slot &sl = step[k];
-            H.rec.push_back(sl.row >= 0 ? sl.row : nr);
-            if (sl.row >= 0)
-                H.rec.push_back((sl.row & (ring - 1)) * S * 8);
-            else
-                H.rec.push_back(tri ? trash : zero);
+            const int row = sl.row >= 0 ? sl.row : nr;
+            const int aux = sl.cont ? 1 : (sl.row >= 0 ? 0 : -1);
+            if (invdiag) {  // backward solve: packed record with 1 / U_ii
+                const int slot = sl.row >= 0 ? (sl.row & (ring - 1)) : ring + 1;  // trash row when idle
+                const int pre = sl.row >= 0 ? prerow[sl.row] : gpcg::kBwdRowMask;
+                const double dv = sl.row >= 0 ? (*invdiag)[sl.row] : 0.0;
+                int32_t w[2];
+                std::memcpy(w, &dv, sizeof dv);
+                H.rec.push_back(row | (slot << gpcg::kBwdRowBits));
+                H.rec.push_back(pre | ((aux + 1) << gpcg::kBwdRowBits));
+                H.rec.push_back(w[0]);
+                H.rec.push_back(w[1]);
+                continue;
+            }
+            H.rec.push_back(row);
+            H.rec.push_back(sl.row >= 0 ? (sl.row & (ring - 1)) * S * 8 : (tri ? trash : zero));
             if (tri) {
                 H.rec.push_back(sl.row >= 0 ? prerow[sl.row] : -1);
-                H.rec.push_back(sl.cont ? 1 : (sl.row >= 0 ? 0 : -1));
+                H.rec.push_back(aux);
             } else {
                 H.rec.push_back(sl.cont ? -2 : (sl.row >= 0 ? prerow[sl.row] : -1));
                 H.rec.push_back(sl.la >= 0 ? sl.la : nr);
             }
-            if (invdiag) H.dinv.push_back(sl.row >= 0 ? (*invdiag)[sl.row] : 0.0);
         }
         // per slot: K values (two to a 16-byte chunk), then K ring offsets
         // (four to a chunk); stored chunk-major, chunk c of slot k at
@@ -473,19 +482,16 @@ Steps prod_steps(int nr, int R, int lead) {
 struct DevProgram {
     int steps = 0, ring = 1;
     DevBuf<int32_t> rec, ent;
-    DevBuf<double> dinv;
     void upload(const HostProg &H, hipStream_t st) {
         steps = H.steps;
         ring = H.ring;
         rec.upload(H.rec.data(), H.rec.size(), st);
         ent.upload(H.ent.data(), H.ent.size(), st);
-        dinv.upload(H.dinv.data(), H.dinv.size(), st);
     }
     gpcg::Program view() const {
         gpcg::Program g{};
         g.rec = (const int4 *)rec.p;
         g.ent = (const int4 *)ent.p;
-        g.dinv = dinv.p;
         g.steps = steps;
         g.ring = ring;
         return g;
@@ -564,7 +570,7 @@ struct gpcg_context {
             const Steps FS = expand(tri_steps(F.rows, R), R, gpcg::kEntTri, hL);
             const Steps BS = expand(tri_steps(B.rows, R), R, gpcg::kEntTri, hU);
             const int wf = ring_needed(FS, hL, true, max_ring);
-            const int wb = ring_needed(BS, hU, true, max_ring);
+            const int wb = ring_needed(BS, hU, true, std::min(max_ring, gpcg::kBwdMaxRing));
             if (wf > 0 && wb > 0) {
                 D->f.upload(pack(FS, R, S_, wf, gpcg::kEntTri, hL, true, nullptr, h_prerow), stream);
                 D->b.upload(pack(BS, R, S_, wb, gpcg::kEntTri, hU, true, &h_invdiag, h_prerow), stream);
@@ -1057,6 +1063,7 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
     return guarded([&] {
         if (!out) fail(GPCG_E_ARG, "out is NULL");
         if (n_bus < 2) fail(GPCG_E_ARG, "need at least two buses");
+        if (n_bus >= gpcg::kBwdRowMask) fail(GPCG_E_UNSUPPORTED, "at most 2^20 - 2 buses");
         if (!br_x) fail(GPCG_E_ARG, "br_x is NULL");
         check_branches(n_bus, m, br_from, br_to, br_x);
         const int nr = n_bus - 1;

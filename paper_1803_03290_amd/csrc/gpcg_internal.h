@@ -49,13 +49,19 @@ constexpr int kEntProd = 8;
 //     ent[(s * 3K/4 + c) * R + rs]: chunks c < K/2 hold the values of
 //     entries 2c and 2c + 1 (doubles), chunks K/2 + c' the LDS byte offsets
 //     of the ring slots (for column 0) of entries 4c' .. 4c' + 3;
-//   dinv[s * R + rs] = 1 / U_ii (backward solve only).
+//   The backward solve packs its records instead (kBwdRowBits-bit row and
+//   pre-order fields), so that 1 / U_ii rides in the same 16-byte load:
+//     rec[s * R + rs] = {row | slot << 20, pre | (aux + 1) << 20, 1 / U_ii}:
+//     slot: the ring slot index of own (own = slot * S * 8); pre: 2^20 - 1
+//     when none; 1 / U_ii: 0 for idle and continuation slots.
 struct Program {
     const int4 *rec;
     const int4 *ent;
-    const double *dinv;
     int steps, ring;
 };
+constexpr int kBwdRowBits = 20;                      // row and pre-order fields of the backward records
+constexpr int kBwdRowMask = (1 << kBwdRowBits) - 1;  // also the "none" pre-order number
+constexpr int kBwdMaxRing = 2048;                    // ring rows of the backward solve (slot + 2 < 2^12)
 
 // Everything one launch of the tile kernel needs.  All pointers are device
 // memory.  Reduced row i is bus i + 1.

@@ -308,17 +308,26 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
 }
 
 // ---- backward: z = U^-1 y, islanded rows zeroed on output, r'z ------------
+// Its records are packed: {row | slot << 20, pre | (aux + 1) << 20, 1 / U_ii}.
+__device__ __forceinline__ int bwd_row(const int4 &h) { return h.x & kBwdRowMask; }
+__device__ __forceinline__ int bwd_pre(const int4 &h) { return h.y & kBwdRowMask; }
+__device__ __forceinline__ bool bwd_cont(const int4 &h) { return ((unsigned)h.y >> kBwdRowBits) == 2u; }
+__device__ __forceinline__ double bwd_dinv(const int4 &h) { return __hiloint2double(h.w, h.z); }
+template <int S>
+__device__ __forceinline__ int bwd_own(const int4 &h) {
+    return (int)(((unsigned)h.x >> kBwdRowBits) * (S * 8));
+}
+
 struct BwdVec {
-    double y, r, dinv;
+    double y, r;
 };
 
 template <int S>
-__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const double *dinv, const Tile &T, int sc) {
-    const unsigned o = row_off<S>(T, h.x, sc);
+__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile &T, int sc) {
+    const unsigned o = row_off<S>(T, bwd_row(h), sc);
     const dvec2 ry = ry_get(T, o);
     v.y = ry.y;
     v.r = ry.x;
-    v.dinv = *dinv;
 }
 template <int S, int D>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
@@ -338,15 +347,15 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
 #pragma unroll
     for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
 #pragma unroll
-    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], g.dinv + (size_t)z0 * R + rs + d * R, T, sc);
+    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
     ring_read(G, ga, ring);
-    double yc = vq[0].y, dv = vq[0].dinv, r = vq[0].r;  // step 0's row
-    bwd_vec<S>(vq[0], hq[D], g.dinv + (size_t)z0 * R + rs + D * R, T, sc);
+    double yc = vq[0].y, dv = bwd_dinv(hq[0]), r = vq[0].r;  // step 0's row
+    bwd_vec<S>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
         const int4 *hb = head_slot<S>(g, sb, rs);
@@ -357,23 +366,24 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
             // A
             const double dot = tree_dot(G, eq[d % E]);
             const double z = (yc - dot) * dv;
-            ring_put(ring, h.y + lane_off, z);
+            ring_put(ring, bwd_own<S>(h) + lane_off, z);
             ring_addr(ga, eq[(d + 1) % E], lane_off);
             ring_read(G, ga, ring);
             __builtin_amdgcn_sched_barrier(0);
             // B
             {
-                const double zm = in_interval(h.z, lo, hi) ? 0.0 : z;
-                y_put(T, row_off<S>(T, h.x, sc), zm);
-                rz += (h.x < T.nr) ? r * zm : 0.0;
-                carry = (h.w == 1) ? carry + dot : 0.0;
+                const int row = bwd_row(h);
+                const double zm = in_interval(bwd_pre(h), lo, hi) ? 0.0 : z;
+                y_put(T, row_off<S>(T, row, sc), zm);
+                rz += (row < T.nr) ? r * zm : 0.0;
+                carry = bwd_cont(h) ? carry + dot : 0.0;
                 const BwdVec v = vq[(d + 1) % D];
                 yc = v.y - carry;
-                dv = v.dinv;
+                dv = bwd_dinv(hq[(d + 1) % H]);
                 r = v.r;
             }
             load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
-            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], g.dinv + (size_t)sb * R + rs + (d + 1 + D) * R, T, sc);
+            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
             hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
