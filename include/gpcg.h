@@ -166,6 +166,10 @@ int gpcg_topology(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *
  * theta_base is NULL, ignored otherwise.
  * stream: a hipStream_t (NULL = the null stream) on which every later
  * operation of the context is enqueued.
+ * Errors: GPCG_E_ARG (fewer than two buses, a branch out of range),
+ * GPCG_E_UNSUPPORTED (2^20 - 1 buses or more, or a matrix or factor
+ * bandwidth whose LDS window exceeds what one wavefront may hold at this
+ * block; number the buses in a banded order).
  * On error *out is NULL and nothing is leaked.
  */
 int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, const int32_t *br_to,
