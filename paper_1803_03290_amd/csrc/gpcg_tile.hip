@@ -292,7 +292,7 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
             {
                 const unsigned o = row_off<S>(T, h.x, sc);
                 ry_put(T, o, r, y);
-                rr += (h.x < T.nr) ? r * r : 0.0;
+                rr = __builtin_fma(r, r, rr);  // idle slots hold the scratch row's r = 0
                 carry = (h.w == 1) ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
                 r = v.r - alpha * v.q;
@@ -375,7 +375,7 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
                 const int row = bwd_row(h);
                 const double zm = in_interval(bwd_pre(h), lo, hi) ? 0.0 : z;
                 y_put(T, row_off<S>(T, row, sc), zm);
-                rz += (row < T.nr) ? r * zm : 0.0;
+                rz = __builtin_fma(r, zm, rz);  // idle slots: r = 0 and 1/U_ii = 0
                 carry = bwd_cont(h) ? carry + dot : 0.0;
                 const BwdVec v = vq[(d + 1) % D];
                 yc = v.y - carry;
@@ -456,13 +456,18 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
             {
                 xp_put(T, lo_, v.x + alpha * v.p, pn);
                 const double dot = gdot(G);
+                const bool cont = h.z == -2;
                 double qv = carry + dot;
-                carry = (h.z == -2) ? carry + dot : 0.0;
+                carry = cont ? carry + dot : 0.0;
                 const double dpc = pf - pt;
                 qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
+                // a continuation's partial sum is not stored, so the scratch
+                // row's q (and with it its r) stays exactly zero; islanded
+                // rows are zero
                 if (in_interval(h.z, lo, hi)) qv = 0.0;
+                qv = cont ? 0.0 : qv;
                 vput(T, VQ, row_off<S>(T, h.x, sc), qv);
-                pq += (h.x < T.nr) ? pown * qv : 0.0;
+                pq = __builtin_fma(pown, qv, pq);  // idle slots read pown from the zero row
             }
             __builtin_amdgcn_sched_barrier(0);
         }
