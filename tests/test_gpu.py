@@ -354,6 +354,17 @@ def test_solve_rhs_grid200(gp, grids, kind):
             assert _iters_close(it[s], k), (c, it[s], k)
 
 
+def test_setup_refuses_too_many_buses(gp):
+    """The backward solve's packed step records hold 20-bit row and
+    pre-order numbers, so setup refuses 2^20 - 1 buses or more (a path here;
+    refused before any device work)."""
+    n = (1 << 20) - 1
+    f = np.arange(n - 1, dtype=np.int32)
+    with pytest.raises(gp.binding.GpcgError) as e:
+        gp.Context(n, f, f + 1, np.full(n - 1, 0.1), np.zeros(n), block=4)
+    assert e.value.code == -6
+
+
 def test_solve_rhs_edges(gp, grids):
     """A zero right-hand side (x = 0 in no iterations), a ragged batch of 70,
     bad outage ids, and the rhs argument checks."""
