@@ -33,15 +33,17 @@ namespace {
 // ---------------------------------------------------------------------------
 // Sweeps.  Each sweep walks its program step by step through a three-stage
 // register pipeline: a step's row record is loaded H = 2D steps ahead, its
-// vector rows D steps ahead and its matrix entries E = 2 steps ahead (they
-// are shared by every wave and sit in L1/L2).  A step first consumes its
+// vector rows D steps ahead and its matrix entries E steps ahead (4 in the
+// triangular solves, 2 in the product; they are shared by every wave and
+// sit in L1/L2).  A step first consumes its
 // pipeline slots and then refills them with later steps, so no register is
 // copied, no load waits on another load still in flight, and a step only
 // waits on the LDS ring that carries the dependencies between rows.
 // Vector-memory counters complete in order, so the loop has no branches
 // around loads and stores: idle slots read and write the tile's scratch row
-// (row n_r) and the ring's trash row, and padding entries are real zero
-// entries in memory.
+// (row n_r), which stays exactly zero in r, q and p, and the ring's trash
+// row, and padding entries are real zero entries pointing at the ring's zero
+// row.
 //
 // A tile stores the pairs {delta, p}, the pairs {r, y / z} and q, each row-major
 // with S columns: a wave's access to one vector row is S contiguous doubles
