@@ -9,7 +9,7 @@
 namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
-constexpr int kVectors = 5;   // per tile: delta, r, p, q, y/z, each (n_r + 1) x S
+constexpr int kVectors = 4;   // per tile: pairs {delta, p} and pairs {r, w} (w: y, z, then q), (n_r + 1) x S each
 // doubles per vector of a tile: (n_r + 1) rows x S columns, rounded up to
 // even so that every vector, and every {delta, p} pair, is 16-byte aligned
 constexpr size_t vec_stride(int n_r, int S) { return ((size_t)(n_r + 1) * S + 1) / 2 * 2; }
@@ -93,7 +93,7 @@ struct PcgParams {
     int tile0;  // first tile of this launch (plain mode launches one tile at a time)
     double tol2;
     int max_iter;
-    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, pairs {r, y / z}, q
+    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, pairs {r, w}
     int32_t *iters_out, *status_out;
     double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
 };

@@ -3,14 +3,17 @@
 // Layout.  Scenarios are grouped S to a tile; one wavefront owns one tile and
 // carries it through the whole preconditioned CG of Section III.A.  Its 64
 // lanes are R x S with R = 64 / S: lane = rs * S + sc treats scenario column
-// sc and row slot rs.  Per tile the workspace holds five vectors: delta (the
-// change of state from the base case), p, r, q = A_c p, and y / z (the
-// forward-solve result, overwritten by the backward-solve result), each
-// (n_r + 1) x S row-major (row n_r is scratch).  delta and p, which only the
+// sc and row slot rs.  Per tile the workspace holds four vectors: delta (the
+// change of state from the base case), p, r, and w, which holds in turn y
+// (the forward-solve result), z (the backward-solve result) and q = A_c p,
+// each (n_r + 1) x S row-major (row n_r is scratch).  delta and p, which only the
 // product sweep touches and always together, are interleaved as pairs
-// {delta, p} per (row, column) in the first two vector slots; r and y / z,
-// which the forward sweep stores together and the backward sweep loads
-// together, as pairs {r, y / z} in the next two; q follows.  A wave touching a row of a vector reads S
+// {delta, p} per (row, column) in the first two vector slots; r and w in the
+// other two as pairs {r, w}, where w holds y after the forward sweep, z after
+// the backward sweep and q after the product (a row's z is last read as a
+// look-ahead row, before the product writes its q).  So the forward sweep
+// loads {r, q} and stores {r, y} with one access each, and the backward
+// sweep loads {r, y} with one.  A wave touching a row of a vector reads S
 // contiguous doubles (pairs), and every matrix entry it reads is shared by
 // the S columns.
 //
@@ -41,16 +44,15 @@ namespace {
 // waits on the LDS ring that carries the dependencies between rows.
 // Vector-memory counters complete in order, so the loop has no branches
 // around loads and stores: idle slots read and write the tile's scratch row
-// (row n_r), which stays exactly zero in r, q and p, and the ring's trash
-// row, and padding entries are real zero entries pointing at the ring's zero
-// row.
+// (row n_r; it holds r = 0 and p = 0, and q = 0 when the forward sweep reads
+// it) and the ring's trash row, and padding entries are real zero entries
+// pointing at the ring's zero row.
 //
-// A tile stores the pairs {delta, p}, the pairs {r, y / z} and q, each row-major
+// A tile stores the pairs {delta, p} and the pairs {r, w}, each row-major
 // with S columns: a wave's access to one vector row is S contiguous doubles
 // (or pairs), and every sweep reads only the vectors it needs.  Vector bases
 // are wave-uniform (scalar registers); a step computes one 32-bit offset for
 // all of them (twice it for the pairs).
-enum : int { VQ = 4 };
 constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
 constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
 
@@ -133,7 +135,7 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
 }
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
-// the {delta, p} pairs at xp, the {r, y / z} pairs at ry, q at v[VQ].
+// the {delta, p} pairs at xp, the {r, w} pairs at ry (w: y, then z, then q).
 struct Tile {
     double *xp, *ry;
     double *v[kVectors];
@@ -145,14 +147,6 @@ struct Tile {
 template <int S>
 __device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
     return ((unsigned)row * S + sc) * 8u;
-}
-
-__device__ __forceinline__ double vget(const Tile &T, int v, unsigned off) {
-    return *(const double *)((const char *)T.v[v] + off);
-}
-
-__device__ __forceinline__ void vput(const Tile &T, int v, unsigned off, double x) {
-    *(double *)((char *)T.v[v] + off) = x;
 }
 
 // the pair {delta, p} at the element offset off of the other vectors
@@ -177,10 +171,6 @@ __device__ __forceinline__ void ry_put(const Tile &T, unsigned off, double r, do
     w.x = r;
     w.y = y;
     *(dvec2 *)((char *)T.ry + 2 * off) = w;
-}
-
-__device__ __forceinline__ double r_get(const Tile &T, unsigned off) {
-    return *(const double *)((const char *)T.ry + 2 * off);
 }
 
 __device__ __forceinline__ double y_get(const Tile &T, unsigned off) {
@@ -243,8 +233,9 @@ struct FwdVec {
 template <int S>
 __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
     const unsigned o = row_off<S>(T, h.x, sc);
-    v.r = r_get(T, o);
-    v.q = vget(T, VQ, o);
+    const dvec2 rq = ry_get(T, o);  // {r, q}: q sits where y and z were
+    v.r = rq.x;
+    v.q = rq.y;
 }
 
 template <int S, int D>
@@ -293,9 +284,12 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
             // B
             {
                 const unsigned o = row_off<S>(T, h.x, sc);
-                ry_put(T, o, r, y);
+                const bool cont = h.w == 1;
+                // a continuation's partial y is not stored: the scratch row's
+                // w is read back as q by later idle slots of this sweep
+                ry_put(T, o, r, cont ? 0.0 : y);
                 rr = __builtin_fma(r, r, rr);  // idle slots hold the scratch row's r = 0
-                carry = (h.w == 1) ? carry + dot : 0.0;
+                carry = cont ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
                 r = v.r - alpha * v.q;
                 rc = r - carry;
@@ -464,11 +458,11 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
                 const double dpc = pf - pt;
                 qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
                 // a continuation's partial sum is not stored, so the scratch
-                // row's q (and with it its r) stays exactly zero; islanded
-                // rows are zero
+                // row's q, as the forward sweep reads it, is exactly zero
+                // (and with it its r); islanded rows are zero
                 if (in_interval(h.z, lo, hi)) qv = 0.0;
                 qv = cont ? 0.0 : qv;
-                vput(T, VQ, row_off<S>(T, h.x, sc), qv);
+                y_put(T, row_off<S>(T, h.x, sc), qv);  // z of this row was read as a look-ahead row
                 pq = __builtin_fma(pown, qv, pq);  // idle slots read pown from the zero row
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -537,8 +531,7 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
             xp_put(T, o, 0.0, 0.0);
-            ry_put(T, o, r0, 0.0);
-            vput(T, VQ, o, 0.0);
+            ry_put(T, o, r0, 0.0);  // q = 0
         }
         bb = rr;
     } else {
@@ -579,15 +572,13 @@ __device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, dou
             rr += r0 * r0;
             const unsigned o = row_off<S>(T, i, sc);
             xp_put(T, o, 0.0, 0.0);
-            ry_put(T, o, r0, 0.0);
-            vput(T, VQ, o, 0.0);
+            ry_put(T, o, r0, 0.0);  // q = 0
         }
     }
     if (rs == 0) {
         const unsigned o = row_off<S>(T, nr, sc);
         xp_put(T, o, 0.0, 0.0);
         ry_put(T, o, 0.0, 0.0);
-        vput(T, VQ, o, 0.0);
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
