@@ -36,9 +36,10 @@ namespace {
 // ---------------------------------------------------------------------------
 // Sweeps.  Each sweep walks its program step by step through a three-stage
 // register pipeline: a step's row record is loaded H = 2D steps ahead, its
-// vector rows D steps ahead and its matrix entries E steps ahead (4 in the
+// vector rows D steps ahead and its matrix entries E steps ahead (8 in the
 // triangular solves, 2 in the product; they are shared by every wave and
-// sit in L1/L2).  A step first consumes its
+// sit in L1/L2; vector-memory counters retire in order, so the wait for a
+// step's entries also waits for every older load).  A step first consumes its
 // pipeline slots and then refills them with later steps, so no register is
 // copied, no load waits on another load still in flight, and a step only
 // waits on the LDS ring that carries the dependencies between rows.
@@ -53,7 +54,7 @@ namespace {
 // (or pairs), and every sweep reads only the vectors it needs.  Vector bases
 // are wave-uniform (scalar registers); a step computes one 32-bit offset for
 // all of them (twice it for the pairs).
-constexpr int kEntAheadTri = 4;   // steps the triangular solves prefetch entries
+constexpr int kEntAheadTri = 8;   // steps the triangular solves prefetch entries
 constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
 
 // The step index as a vector register the compiler cannot see through.
