@@ -6,6 +6,8 @@ column, so reduced row ``k`` is bus ``k + 1``.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as sla
@@ -29,18 +31,28 @@ def susceptance_full(grid, shunt=None) -> sp.csr_matrix:
     shunt susceptances are added to the diagonal, which gives the B'' of
     eq. (5) (reactor sign, so that B'' stays positive definite).
     Parallel branches simply add up.
+
+    Every entry is the exact sum of its terms (the rounded 1/x_e of each
+    branch, and the shunt) rounded once to FP64 (``math.fsum``), so the
+    matrix does not depend on the order in which branches are visited.
     """
     n = grid.n
-    f = grid.br_from.astype(np.int64)
-    t = grid.br_to.astype(np.int64)
     b = 1.0 / np.asarray(grid.x, dtype=np.float64)
-    rows = np.concatenate([f, t, f, t])
-    cols = np.concatenate([t, f, f, t])
-    vals = np.concatenate([-b, -b, b, b])
-    B = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
-    B.sum_duplicates()
+    terms = {}
+    for e in range(grid.m):
+        i, j, v = int(grid.br_from[e]), int(grid.br_to[e]), float(b[e])
+        terms.setdefault((i, i), []).append(v)
+        terms.setdefault((j, j), []).append(v)
+        terms.setdefault((i, j), []).append(-v)
+        terms.setdefault((j, i), []).append(-v)
     if shunt is not None:
-        B = (B + sp.diags(np.asarray(shunt, dtype=np.float64))).tocsr()
+        for k, v in enumerate(np.asarray(shunt, dtype=np.float64)):
+            terms.setdefault((k, k), []).append(float(v))
+    keys = sorted(terms)
+    rows = np.array([k[0] for k in keys], dtype=np.int64)
+    cols = np.array([k[1] for k in keys], dtype=np.int64)
+    vals = np.array([math.fsum(terms[k]) for k in keys], dtype=np.float64)
+    B = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
     B.sort_indices()
     return B
 
@@ -222,15 +234,26 @@ def scenario(grid, c: int, A: sp.csr_matrix | None = None, rhs=None, redispatch_
     return out
 
 
-def true_residual(grid, Ac: sp.csr_matrix, theta: np.ndarray, Pp: np.ndarray, island: np.ndarray) -> float:
-    """Relative residual ||P'_M - A_c[M,M] theta_M|| / ||P'_M||, in extended
-    precision, over the main-system rows."""
-    idx = np.flatnonzero(~island[1:])
+def true_residual(grid, A: sp.csr_matrix, c: int, theta: np.ndarray, Pp: np.ndarray, island: np.ndarray) -> float:
+    """Relative residual ||P'_M - A_c[M,M] theta_M|| / ||P'_M|| over the
+    main-system rows, in extended precision.
+
+    A_c = A - b_c u u^T is applied with the outage's change taken exactly
+    (Section IV.B: four entries change by +-b_c, b_c = 1/x_c as it enters A):
+    A_c[M,M] theta_M = (A theta~)_M - b_c (u'theta~) u_M with theta~ the
+    angles zeroed outside M, all in ``longdouble``.
+    """
+    main = ~np.asarray(island, bool)[1:]
+    idx = np.flatnonzero(main)
     if len(idx) == 0:
         return 0.0
-    Amm = Ac[idx][:, idx].tocsr()
-    b = Pp[1:][idx]
-    r = _residual_ld(Amm, theta[1:][idx], b)
-    nb = float(np.sqrt(np.sum(np.asarray(b, np.longdouble) ** 2)))
-    nr = float(np.sqrt(np.sum(r ** 2)))
+    th = np.where(main, np.asarray(theta, np.float64)[1:], 0.0).astype(np.longdouble)
+    r = np.asarray(Pp, np.float64)[1:].astype(np.longdouble) - A.astype(np.longdouble) @ th
+    if c >= 0:
+        u = _u_reduced(grid, c).astype(np.longdouble)
+        bc = np.longdouble(1.0 / grid.x[c])
+        r = r + bc * (u @ th) * u
+    b = np.asarray(Pp, np.longdouble)[1:][idx]
+    nb = float(np.sqrt(np.sum(b ** 2)))
+    nr = float(np.sqrt(np.sum(r[idx] ** 2)))
     return nr / nb if nb > 0 else nr

@@ -83,39 +83,76 @@ void check_branches(int n_bus, int m, const int32_t *from, const int32_t *to, co
 }
 
 // ---------------------------------------------------------------------------
-// Reduced susceptance matrix (slack = bus 0 dropped).
+// Correctly rounded sum of doubles: the exact sum is carried as a list of
+// non-overlapping partials (Shewchuk, "Adaptive precision floating-point
+// arithmetic and fast robust geometric predicates", 1997), which are then
+// added from the largest down; a final check settles the half-way case, where
+// the rounding of the leading pair has to be decided by the sign of the rest.
+double exact_sum(const std::vector<double> &terms) {
+    std::vector<double> part;
+    for (double x : terms) {
+        size_t k = 0;
+        for (double y : part) {
+            if (std::fabs(x) < std::fabs(y)) std::swap(x, y);
+            const double hi = x + y;
+            const double lo = y - (hi - x);
+            if (lo != 0.0) part[k++] = lo;
+            x = hi;
+        }
+        part.resize(k);
+        part.push_back(x);
+    }
+    if (part.empty()) return 0.0;
+    size_t n = part.size() - 1;
+    double hi = part[n], lo = 0.0;
+    while (n > 0) {
+        const double x = hi, y = part[--n];
+        hi = x + y;
+        lo = y - (hi - x);
+        if (lo != 0.0) break;
+    }
+    if (n > 0 && ((lo < 0.0 && part[n - 1] < 0.0) || (lo > 0.0 && part[n - 1] > 0.0))) {
+        const double y = 2.0 * lo, x = hi + y;
+        if (y == x - hi) hi = x;
+    }
+    return hi;
+}
+
+// ---------------------------------------------------------------------------
+// Reduced susceptance matrix (slack = bus 0 dropped).  Every entry is the
+// exact sum of its terms (each branch's rounded 1 / x, the shunt) rounded
+// once, so the matrix does not depend on the order of the branch table.
 int assemble(int n_bus, int m, const int32_t *from, const int32_t *to, const double *x, const double *shunt,
              std::vector<int32_t> &rowptr, std::vector<int32_t> &col, std::vector<double> &val) {
     const int nr = n_bus - 1;
-    // adjacency of reduced rows with summed susceptances, via per-row buckets
+    // per reduced row: (column, term) pairs, the diagonal's terms included
     std::vector<std::vector<std::pair<int, double>>> rows(nr);
-    std::vector<double> diag(nr, 0.0);
     for (int e = 0; e < m; ++e) {
         const double b = 1.0 / x[e];
         const int f = from[e] - 1, t = to[e] - 1;
-        if (f >= 0) diag[f] += b;
-        if (t >= 0) diag[t] += b;
+        if (f >= 0) rows[f].push_back({f, b});
+        if (t >= 0) rows[t].push_back({t, b});
         if (f >= 0 && t >= 0) {
             rows[f].push_back({t, -b});
             rows[t].push_back({f, -b});
         }
     }
-    if (shunt)
-        for (int i = 0; i < nr; ++i) diag[i] += shunt[i + 1];
     rowptr.assign(nr + 1, 0);
     col.clear();
     val.clear();
+    std::vector<double> terms;
     for (int i = 0; i < nr; ++i) {
         auto &r = rows[i];
-        r.push_back({i, diag[i]});
-        std::sort(r.begin(), r.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
-        for (size_t k = 0; k < r.size(); ++k) {
-            if (!col.empty() && (int)col.size() > rowptr[i] && col.back() == r[k].first)
-                val.back() += r[k].second;  // parallel branches add up
-            else {
-                col.push_back(r[k].first);
-                val.push_back(r[k].second);
-            }
+        if (shunt) r.push_back({i, shunt[i + 1]});
+        r.push_back({i, 0.0});  // every row keeps its diagonal entry
+        std::stable_sort(r.begin(), r.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+        for (size_t k = 0; k < r.size();) {
+            size_t k1 = k;
+            terms.clear();
+            while (k1 < r.size() && r[k1].first == r[k].first) terms.push_back(r[k1++].second);
+            col.push_back(r[k].first);
+            val.push_back(exact_sum(terms));  // parallel branches add up
+            k = k1;
         }
         rowptr[i + 1] = (int32_t)col.size();
     }

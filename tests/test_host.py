@@ -32,13 +32,19 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("key", ["grid200", "grid2k", "grid10k"])
 def test_assembly_matches_oracle(grids, key):
+    """Both sides round every entry once from its exact sum, so the reduced
+    B' (and B'' with the 10k grid's shunts) agree bit for bit."""
     g = grids[key]
     A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
     Ao = oracle.reduced(oracle.susceptance_full(g))
-    assert (A != 0).nnz == (Ao != 0).nnz
     np.testing.assert_array_equal(A.indptr, Ao.indptr)
     np.testing.assert_array_equal(A.indices, Ao.indices)
-    np.testing.assert_allclose(A.data, Ao.data, rtol=1e-15)
+    np.testing.assert_array_equal(A.data, Ao.data)
+    if g.bsh is not None:
+        A = gp.assemble(g.n, g.br_from, g.br_to, g.x, g.bsh).to_scipy()
+        Ao = oracle.reduced(oracle.susceptance_full(g, g.bsh))
+        np.testing.assert_array_equal(A.indices, Ao.indices)
+        np.testing.assert_array_equal(A.data, Ao.data)
 
 
 def test_assembly_with_shunts(grids):
@@ -46,14 +52,41 @@ def test_assembly_with_shunts(grids):
     bsh = np.linspace(0.0, 0.05, g.n)
     A = gp.assemble(g.n, g.br_from, g.br_to, g.x, bsh).to_scipy()
     Ao = oracle.reduced(oracle.susceptance_full(g, bsh))
-    np.testing.assert_allclose(A.toarray(), Ao.toarray(), rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(A.toarray(), Ao.toarray())
 
 
 def test_assembly_parallel_branches():
     g = gridgen.hand_grid("parallel")
     A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
     Ao = oracle.reduced(oracle.susceptance_full(g))
-    np.testing.assert_allclose(A.toarray(), Ao.toarray(), rtol=1e-15)
+    np.testing.assert_array_equal(A.toarray(), Ao.toarray())
+
+
+def test_assembly_entries_are_correctly_rounded_sums():
+    """A star where the order of the additions decides the last bit: bus 1
+    meets branches of susceptance 1, 2^-53 and 2^-53 (and a parallel pair
+    to bus 2).  Left to right in FP64 the diagonal is 1 (each 2^-53 is a
+    tie that rounds back to 1); the exact sum 1 + 2^-52 is representable.
+    Both assemblies must give the exact value, checked with rationals,
+    under every order of the branch table."""
+    from fractions import Fraction
+    import itertools
+
+    pairs = [(0, 1), (1, 2), (1, 3), (1, 2), (0, 3)]
+    x = [1.0, 2.0 ** 53, 2.0 ** 53, 3.0, 7.0]
+    exact_11 = sum(Fraction(1) / Fraction(v) for v in x[:4])
+    exact_12 = -(Fraction(1) / Fraction(x[1]) + Fraction(1) / Fraction(x[3]))
+    for perm in itertools.permutations(range(len(pairs))):
+        pr = np.array([pairs[k] for k in perm], np.int32)
+        xx = np.array([x[k] for k in perm])
+        g = gridgen.Grid("star", 4, pr[:, 0].copy(), pr[:, 1].copy(), xx, np.zeros(4))
+        A = gp.assemble(4, g.br_from, g.br_to, g.x).to_scipy().toarray()
+        Ao = oracle.reduced(oracle.susceptance_full(g)).toarray()
+        assert A[0, 0] == float(exact_11) and Ao[0, 0] == float(exact_11), perm
+        assert A[0, 1] == float(exact_12) and Ao[0, 1] == float(exact_12), perm
+    # the naive left-to-right sum of the first three terms loses the last bit
+    assert (1.0 + 2.0 ** -53) + 2.0 ** -53 == 1.0
+    assert float(Fraction(1) + 2 * Fraction(1, 2 ** 53)) == 1.0 + 2.0 ** -52
 
 
 @pytest.mark.parametrize("key", ["grid200", "grid2k"])

@@ -356,7 +356,64 @@ def test_pcg_matches_direct(grids):
         p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=1e-12)
         assert np.abs(p["theta"] - d["theta"]).max() < 1e-10
         assert p["status"] == d["status"]
-        assert oracle.true_residual(g, d["Ac"], p["theta"], d["Pp"], d["island"]) < 1e-10
+        assert oracle.true_residual(g, A, int(c), p["theta"], d["Pp"], d["island"]) < 1e-10
+
+
+# ------------------------------------------------------- true residual
+
+
+def test_true_residual_closed_form_ring3():
+    """ring3 without branch (1,2): A_c = (1/a) I, so theta* + eps e_1 has
+    residual A_c (eps e_1) = (eps / a) e_1 and a relative residual of
+    (eps / a) / ||P_M||; theta* itself is at rounding level."""
+    g = gridgen.hand_grid("ring3")
+    _, A = oracle.base_case(g)
+    d = oracle.scenario(g, 2, A)
+    assert oracle.true_residual(g, A, 2, d["theta"], d["Pp"], d["island"]) < 1e-15
+    a, eps = 0.1, 1e-6
+    th = d["theta"].copy()
+    th[1] += eps
+    expect = (eps / a) / np.hypot(g.P[1], g.P[2])
+    assert oracle.true_residual(g, A, 2, th, d["Pp"], d["island"]) == pytest.approx(expect, rel=1e-9)
+
+
+def test_true_residual_closed_form_island():
+    """path5 without the bridge (1,2): the main system is bus 1 alone (plus
+    the slack), A_c[M,M] = [1/x_01] = [10], and the re-dispatch leaves
+    P'_1 = 0.5 (1 + (-0.3) / 0.5) = 0.2.  theta_1* + eps with arbitrary
+    values on the island has relative residual 10 eps / 0.2 = 50 eps: the
+    island's rows and angles do not enter."""
+    g = gridgen.hand_grid("path5")
+    _, A = oracle.base_case(g)
+    d = oracle.scenario(g, 1, A)
+    assert d["Pp"][1] == pytest.approx(0.2, rel=1e-15)
+    eps = 1e-7
+    th = d["theta"].copy()
+    th[1] += eps
+    th[2:] = [3.0, -7.0, 11.0]
+    assert oracle.true_residual(g, A, 1, th, d["Pp"], d["island"]) == pytest.approx(50 * eps, rel=1e-9)
+
+
+def test_true_residual_pins_catch_mistakes(monkeypatch):
+    """Planted mistakes: a residual that ignored the island (all rows kept)
+    or dropped the outage's rank-1 term misses the closed forms above."""
+    g = gridgen.hand_grid("path5")
+    _, A = oracle.base_case(g)
+    d = oracle.scenario(g, 1, A)
+    th = d["theta"].copy()
+    th[1] += 1e-7
+    th[2:] = [3.0, -7.0, 11.0]
+    no_mask = oracle.true_residual(g, A, 1, th, d["Pp"], np.zeros(g.n, bool))
+    assert abs(no_mask - 50e-7) > 1e-3 * 50e-7
+    g3 = gridgen.hand_grid("ring3")
+    _, A3 = oracle.base_case(g3)
+    d3 = oracle.scenario(g3, 2, A3)
+    th3 = d3["theta"].copy()
+    th3[1] += 1e-6
+    expect = (1e-6 / 0.1) / np.hypot(g3.P[1], g3.P[2])
+    monkeypatch.setattr(osys, "_u_reduced", lambda grid, c: np.zeros(grid.n - 1))
+    dropped = oracle.true_residual(g3, A3, 2, th3, d3["Pp"], d3["island"])
+    assert abs(dropped - expect) > 1e-3 * expect
 
 
 # ------------------------------------------------- planted mistakes (CPU)
