@@ -52,14 +52,19 @@ def _apply_prec(Lf, U, r, mask):
     return np.where(mask, z, 0.0)
 
 
-def pcg_textbook(A, b, L, U, x0=None, r0=None, mask=None, tol=1e-12, max_iter=10000, bnorm=None):
+def pcg_textbook(A, b, L, U, x0=None, r0=None, mask=None, tol=1e-12, max_iter=10000, bnorm=None, dot=None):
     """PCG on A x = b with preconditioner M = (L+I) U.
 
     Either ``x0`` (then r0 = b - A x0) or ``r0`` directly may be given.  Rows
     where ``mask`` is False are held at zero.  Returns (x, iters, status,
     history of ||r_k||).  ``iters`` counts the step-length updates taken
-    (0 when the starting residual already passes).
+    (0 when the starting residual already passes).  ``dot(u, v)`` forms the
+    inner products and norms (default: NumPy's ``u @ v``); any correctly
+    computed inner product is a valid choice, and the choice only moves
+    rounding.
     """
+    if dot is None:
+        dot = lambda u, v: float(u @ v)  # noqa: E731
     n = A.shape[0]
     Lf = (L + sp.eye(n, format="csr")).tocsr()
     U = U.tocsr()
@@ -71,16 +76,16 @@ def pcg_textbook(A, b, L, U, x0=None, r0=None, mask=None, tol=1e-12, max_iter=10
         r = np.array(r0, dtype=np.float64)
     r = np.where(mask, r, 0.0)
     bnorm = float(np.linalg.norm(np.where(mask, b, 0.0))) if bnorm is None else bnorm
-    hist = [float(np.linalg.norm(r))]
+    hist = [float(np.sqrt(dot(r, r)))]
     if hist[0] <= tol * bnorm:
         return x, 0, STATUS_CONVERGED, hist
     z = _apply_prec(Lf, U, r, mask)
     p = z.copy()
-    rho = float(r @ z)
+    rho = dot(r, z)
     for k in range(1, max_iter + 1):
         q = A @ p
         q = np.where(mask, q, 0.0)
-        sigma = float(p @ q)
+        sigma = dot(p, q)
         if not np.isfinite(sigma) or not np.isfinite(rho):
             return x, k - 1, STATUS_NONFINITE, hist
         if sigma <= 0.0:
@@ -88,20 +93,20 @@ def pcg_textbook(A, b, L, U, x0=None, r0=None, mask=None, tol=1e-12, max_iter=10
         alpha = rho / sigma
         x = x + alpha * p
         r = r - alpha * q
-        hist.append(float(np.linalg.norm(r)))
+        hist.append(float(np.sqrt(dot(r, r))))
         if not np.isfinite(hist[-1]):
             return x, k, STATUS_NONFINITE, hist
         if hist[-1] <= tol * bnorm:
             return x, k, STATUS_CONVERGED, hist
         z = _apply_prec(Lf, U, r, mask)
-        rho_new = float(r @ z)
+        rho_new = dot(r, z)
         beta = rho_new / rho
         rho = rho_new
         p = z + beta * p
     return x, max_iter, STATUS_MAX_ITER, hist
 
 
-def pcg_correction(Ac, b_red, theta_b_red, L, U, mask, tol=1e-12, max_iter=10000):
+def pcg_correction(Ac, b_red, theta_b_red, L, U, mask, tol=1e-12, max_iter=10000, dot=None):
     """Correction-form PCG of one scenario on the reduced system.
 
     Solves A_c delta = r0 with r0 = b - A_c theta_b (extended precision) on
@@ -115,12 +120,14 @@ def pcg_correction(Ac, b_red, theta_b_red, L, U, mask, tol=1e-12, max_iter=10000
           - Ac.astype(np.longdouble) @ np.asarray(thb, np.longdouble))
     r0 = np.where(mask, np.asarray(r0, np.float64), 0.0)
     bnorm = float(np.linalg.norm(np.where(mask, b_red, 0.0)))
-    d, its, st, hist = pcg_textbook(Ac, b_red, L, U, r0=r0, mask=mask, tol=tol, max_iter=max_iter, bnorm=bnorm)
+    d, its, st, hist = pcg_textbook(Ac, b_red, L, U, r0=r0, mask=mask, tol=tol, max_iter=max_iter, bnorm=bnorm,
+                                    dot=dot)
     th = np.where(mask, thb + d, 0.0)
     return th, its, st, hist
 
 
-def scenario_pcg(grid, c, A, L, U, theta_b, tol=1e-12, max_iter=10000, rhs=None, redispatch_islands=True):
+def scenario_pcg(grid, c, A, L, U, theta_b, tol=1e-12, max_iter=10000, rhs=None, redispatch_islands=True,
+                 dot=None):
     """One outage scenario solved by the paper's method: island detection,
     re-dispatch, then PCG from the base state with the base ILU factors.
 
@@ -136,7 +143,7 @@ def scenario_pcg(grid, c, A, L, U, theta_b, tol=1e-12, max_iter=10000, rhs=None,
         Pp[island] = 0.0
     Ac = outage_matrix(grid, A, c)
     mask = ~island[1:]
-    th_red, its, st, hist = pcg_correction(Ac, Pp[1:], theta_b[1:], L, U, mask, tol, max_iter)
+    th_red, its, st, hist = pcg_correction(Ac, Pp[1:], theta_b[1:], L, U, mask, tol, max_iter, dot=dot)
     if st == STATUS_CONVERGED and island.any():
         st = STATUS_ISLANDED_NO_GEN if nogen else STATUS_CONVERGED_ISLANDED
     th = np.zeros(grid.n)

@@ -4,11 +4,14 @@ Bars (each derived from the arithmetic it checks):
   * angles: |theta_gpu - theta_oracle|_inf <= 1e-8 rad;
   * flows:  |f_gpu - f_oracle| * x_e <= 2e-8;
   * island flags, bridge flags and scenario status: bit-exact;
-  * iterations: within max(2, 2 %) of the oracle's textbook PCG on the same
-    numbering and factors (both stop where the recursive residual crosses
-    tol ||b||; near a 1e-12 threshold the crossing step moves with the
-    summation order of equally valid roundings);
-  * true relative residual (double-double) <= 1e-10.
+  * iterations: within max(3, ceil(6 %)) of the oracle's textbook PCG on
+    the same numbering and factors (both stop where the recursive residual
+    crosses tol ||b||; that step moves with the summation order of equally
+    valid roundings: the oracle's own PCG under three valid inner products
+    differs by up to 5 iterations at 2k and 10 at 10k, see
+    test_iteration_spread_between_summation_orders);
+  * true relative residual (double-double) <= 1e-10, and equal to the
+    oracle's extended-precision true residual of the same angles within 1 %.
 """
 import numpy as np
 import pytest
@@ -25,7 +28,13 @@ RESID_TOL = 1e-10
 
 
 def _iters_close(a, b):
-    return abs(int(a) - int(b)) <= max(2, int(np.ceil(0.02 * max(int(a), int(b)))))
+    return abs(int(a) - int(b)) <= max(3, int(np.ceil(0.06 * max(int(a), int(b)))))
+
+
+def _resid_close(gpu, orc):
+    """The device's double-double true residual against the oracle's
+    extended-precision one of the same angles."""
+    return abs(gpu - orc) <= 1e-2 * orc + 1e-15
 
 
 @pytest.fixture(scope="module")
@@ -66,6 +75,8 @@ def _check_against_direct(g, A, outages, res, angle_tol=ANGLE_TOL, rhs=None, red
             ferr = np.abs(res["flows"][s] - d["flows"]) * g.x
             assert ferr.max() <= FLOW_TOL, (c, ferr.max())
         assert res["resid"][s] <= RESID_TOL, (c, res["resid"][s])
+        orc = oracle.true_residual(g, A, int(c), res["x"][s], d["Pp"], d["island"])
+        assert _resid_close(res["resid"][s], orc), (c, res["resid"][s], orc)
 
 
 # ------------------------------------------------------------ hand grids
@@ -197,26 +208,40 @@ def test_spmm_against_numpy(gp, grids):
 # ---------------------------------------------------- 2,000-bus grid
 
 
+def _check_all(g, A, outs, res, gp, rhs=None, shunt=None, redispatch=True, angle_tol=ANGLE_TOL):
+    """Every scenario against the oracle (CPU worker pool): angles, flows,
+    island flags and statuses, and the device's true residual against the
+    oracle's of the same angles."""
+    from oracle_pool import compare_all
+
+    out = compare_all(g, A, outs, res, rhs=rhs, shunt=shunt, redispatch=redispatch)
+    bad = np.flatnonzero(out["angle"] > angle_tol)
+    assert len(bad) == 0, ("angles", outs[bad[:5]], out["angle"][bad[:5]], out["angle"].max())
+    if res.get("flows") is not None:
+        assert out["flow"].max() <= FLOW_TOL, ("flows", out["flow"].max())
+    assert out["island_ok"].all(), ("island", outs[~out["island_ok"]][:5])
+    np.testing.assert_array_equal(res["status"], out["status"])
+    assert res["resid"].max() <= RESID_TOL
+    close = np.abs(res["resid"] - out["resid"]) <= 1e-2 * out["resid"] + 1e-15
+    assert close.all(), ("resid", outs[~close][:5], res["resid"][~close][:5], out["resid"][~close][:5])
+    return out
+
+
 @pytest.mark.parametrize("block,tol", [(64, 1e-12), (4, 5e-11)])
 def test_grid2k_all_outages_batched(gp, grids, block, tol):
-    """The benchmark workload at its full size; block 4 with the recursive
-    stop at 5e-11 is the launch the benchmark times.  Every island flag
-    checked bit-exact and every true residual against the bar, angles and
-    flows on a seeded sample of 120 outages, iterations on 12."""
+    """Every outage of the 2,000-bus grid in one launch: angles, flows,
+    island flags, statuses and true residuals of all 2,800 against the
+    oracle; iterations on 12 against its textbook PCG.  Block 4 with the
+    recursive stop at 5e-11 is the launch that meets the residual bar at
+    the lowest cost on this grid."""
     g = grids["grid2k"]
     thb, A = oracle.base_case(g)
     L, U = oracle.ilu0(A)
     ctx = _ctx(gp, g, block=block)
     outs = np.arange(g.m)
     res = _run(gp, ctx, g, outs, tol=tol)
-    isb, _ = ctx.base()
-    for c in outs:
-        np.testing.assert_array_equal(res["island"][c].astype(bool), oracle.island_of(g, int(c)))
-    assert res["resid"].max() <= RESID_TOL
-    rng = np.random.default_rng(7)
-    sample = np.sort(rng.choice(g.m, 120, replace=False))
-    _check_against_direct(g, A, sample, {k: (v[sample] if v is not None else None) for k, v in res.items()})
-    for c in sample[:12]:
+    _check_all(g, A, outs, res, gp)
+    for c in np.sort(np.random.default_rng(7).choice(g.m, 12, replace=False)):
         p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=tol)
         assert _iters_close(res["iters"][c], p["iters"]), (c, res["iters"][c], p["iters"])
 
@@ -225,40 +250,19 @@ def test_grid2k_all_outages_batched(gp, grids, block, tol):
 
 
 def test_grid10k_all_outages(gp, grids):
-    """Every outage of the 10,000-bus grid in one launch (block 16): island
-    flags of all 13,500 outages bit-exact against the brute-force component
-    pass, every status and true residual against the bar, angles and flows
-    on a seeded sample of 60.
-
-    The recursive stop is 1e-12.  At this size the 5e-11 stop that meets the
-    residual bar does not meet the angle bar: outage 5132 then ends 2.2e-7
-    rad from the direct solution, in the oracle's own textbook PCG as on the
-    device.
-
-    Both sides solve the same matrix: the context is given the oracle's
-    assembled A (the C ABI takes the base matrix as an input).  At this size
-    the solution moves by about 1.9e-8 rad when the diagonal sums of A are
-    rounded in another order (a last-bit change in 1,415 entries), more than
-    the angle bar, so the library's own assembly (checked entry by entry
-    against the oracle's on the CPU) cannot be compared at 1e-8 here."""
+    """Every outage of the 10,000-bus grid in one launch at the benchmark's
+    block (8) and stop (1e-12), on the library's own assembly and ILU(0):
+    angles, flows, island flags, statuses and true residuals of all 13,500
+    outages against the oracle's direct solve.  The two assemblies are bit
+    identical (every entry rounded once from its exact sum), so both sides
+    solve the same matrix."""
     g = grids["grid10k"]
     thb, A = oracle.base_case(g)
-    ctx = _ctx(gp, g, block=16, A=A)
+    ctx = _ctx(gp, g, block=8)
     assert np.abs(ctx.base()[1] - thb).max() <= 1e-9
     outs = np.arange(g.m)
     res = _run(gp, ctx, g, outs, tol=1e-12)
-    assert res["resid"].max() <= RESID_TOL
-    for c in outs:
-        isl = oracle.island_of(g, int(c))
-        np.testing.assert_array_equal(res["island"][c].astype(bool), isl, err_msg=f"outage {c}")
-        nogen = oracle.redispatch(g.P, isl)[1]
-        expect = 0 if not isl.any() else (gp.ISLANDED_NO_GEN if nogen else gp.CONVERGED_ISLANDED)
-        assert res["status"][c] == expect, (c, res["status"][c], expect)
-    rng = np.random.default_rng(13)
-    sample = np.sort(rng.choice(g.m, 60, replace=False))
-    islanding = np.flatnonzero(res["island"].any(axis=1))
-    sample = np.union1d(sample, islanding[:4])
-    _check_against_direct(g, A, sample, {k: (v[sample] if v is not None else None) for k, v in res.items()})
+    _check_all(g, A, outs, res, gp)
 
 
 # --------------------------------------------------------- B'' context
@@ -282,26 +286,15 @@ def test_bpp_context(gp, grids):
 
 def test_bpp_grid10k_all_outages(gp, grids):
     """B'' (the Q-V system, with the 10,000-bus grid's shunts and reactive
-    injections) for every outage in one launch at block 8: island flags and
-    statuses of all 13,500 outages against the brute-force component pass,
-    every true residual against the bar, magnitudes on a seeded sample of 40
-    against the direct solve (both sides on the oracle's assembled B'')."""
+    injections) for every outage in one launch at block 8, on the library's
+    own assembly: magnitudes, island flags, statuses and true residuals of
+    all 13,500 outages against the oracle's direct solve."""
     g = grids["grid10k"]
     _, A = oracle.base_case(g, rhs=g.Q, shunt=g.bsh)
-    ctx = _ctx(gp, g, block=8, kind=1, shunt=g.bsh, rhs=g.Q, A=A)
+    ctx = _ctx(gp, g, block=8, kind=1, shunt=g.bsh, rhs=g.Q)
     outs = np.arange(g.m)
     res = _run(gp, ctx, g, outs, rhs=g.Q)
-    assert res["resid"].max() <= RESID_TOL
-    for c in outs:
-        isl = oracle.island_of(g, int(c))
-        np.testing.assert_array_equal(res["island"][c].astype(bool), isl, err_msg=f"outage {c}")
-        assert res["status"][c] == (gp.CONVERGED_ISLANDED if isl.any() else 0), (c, res["status"][c])
-    rng = np.random.default_rng(17)
-    sample = np.sort(rng.choice(g.m, 40, replace=False))
-    for c in sample:
-        d = oracle.scenario(g, int(c), A, rhs=g.Q, redispatch_islands=False, shunt=g.bsh)
-        err = np.abs(res["x"][c] - d["theta"]).max()
-        assert err <= ANGLE_TOL, (c, err)
+    _check_all(g, A, outs, res, gp, rhs=g.Q, shunt=g.bsh, redispatch=False)
 
 
 # ------------------------------------------- stand-alone product, full size
@@ -736,13 +729,11 @@ def test_batch_full_uneven_workload(gp, grids):
     a seeded sample of 60 outages per grid the status against the
     brute-force component pass and re-dispatch rule.  The angles and flows of
     that sample come from the same batch at the 1e-12 stop (on the large
-    grids the 5e-11 stop meets the residual bar but not the angle bar), with
-    both sides on the oracle's assembled matrices (on the large grids a
-    last-bit change of the assembled diagonal moves the solution by more than
-    the angle bar)."""
+    grids the 5e-11 stop meets the residual bar but not the angle bar), on
+    the library's own assembly (bit identical to the oracle's)."""
     rng = np.random.default_rng(31)
     samples = {n: np.sort(rng.choice(grids[n].m, 60, replace=False)) for n in UNEVEN_ALL}
-    ctxs, outs, rhs = _batch_inputs(gp, UNEVEN_ALL, grids, 4, oracle_matrix=True)
+    ctxs, outs, rhs = _batch_inputs(gp, UNEVEN_ALL, grids, 4)
     for tol in (5e-11, 1e-12):
         b = gp.Batch(ctxs, outs, rhs, block=4, tol=tol)
         b.run()
