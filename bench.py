@@ -62,6 +62,11 @@ def own_work_bytes(info: dict, scen_iters, tile_iters, m: int) -> float:
     return vec + mat + io
 
 
+def kernel_digest() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 

@@ -227,13 +227,14 @@ def _check_all(g, A, outs, res, gp, rhs=None, shunt=None, redispatch=True, angle
     return out
 
 
-@pytest.mark.parametrize("block,tol", [(64, 1e-12), (4, 5e-11)])
+@pytest.mark.parametrize("block,tol", [(64, 1e-12), (4, 1e-12)])
 def test_grid2k_all_outages_batched(gp, grids, block, tol):
     """Every outage of the 2,000-bus grid in one launch: angles, flows,
     island flags, statuses and true residuals of all 2,800 against the
-    oracle; iterations on 12 against its textbook PCG.  Block 4 with the
-    recursive stop at 5e-11 is the launch that meets the residual bar at
-    the lowest cost on this grid."""
+    oracle; iterations on 12 against its textbook PCG.  Block 4 is this
+    grid's fastest launch.  The stop is 1e-12: at 5e-11 (which meets the
+    residual bar) 7 of the 2,800 outages end 1.0e-8 to 1.4e-8 rad from the
+    direct solution."""
     g = grids["grid2k"]
     thb, A = oracle.base_case(g)
     L, U = oracle.ilu0(A)
