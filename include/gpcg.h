@@ -222,6 +222,29 @@ int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, co
                              int32_t *status_out, uint8_t *island_out, double *resid_out);
 
 /*
+ * gpcg_solve_contingencies without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * gpcg_solve_contingencies (bit for bit); its workspace (the tiles' vectors,
+ * 4 (n_r + 1) S doubles per tile of S scenarios, the re-dispatch factors and
+ * the scenario ordering's buffers) is carved from a fixed device array of
+ * GPCG_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends, instead of the context's own growable workspace.
+ *   Limit: a call whose workspace exceeds that size fails with
+ *   GPCG_E_UNSUPPORTED before anything is enqueued (about 1,000 outages of a
+ *   2,000-bus grid at block 4 fit; split larger lists into several calls).
+ *   Sharing: every call on one GPU uses the same array, from any context, and
+ *   the array keeps the last call's contents (nothing in it needs to start at
+ *   zero).  Calls that overlap on one GPU (on different streams or threads)
+ *   race on it; order them on one stream.  gpcg_get_order after such a call
+ *   reads the order from the array, so it must come before the next one.
+ */
+#define GPCG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gpcg_solve_contingencies_noalloc(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                                     int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out,
+                                     int32_t *status_out, uint8_t *island_out, double *resid_out);
+
+/*
  * The batched solve with a right-hand side of its own for every scenario,
  * as the adjoint of a screening loss and the half-iterations of the
  * fast-decoupled power flow need (Section III: eqs. (4)-(5) solved for a

@@ -62,6 +62,8 @@ SIGNATURES = {
     "gpcg_solve_contingencies": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
                                            _VP, _VP]),
     "gpcg_solve_plain": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_solve_contingencies_noalloc": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, C.c_int32, _VP, _VP, _VP,
+                                                   _VP, _VP, _VP]),
     "gpcg_solve_rhs": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP, _VP, _VP, _VP,
                                  _VP]),
     "gpcg_overload_gradients": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_double, C.c_double, C.c_int32, _VP,
@@ -275,16 +277,18 @@ class Context:
         return out
 
     def solve(self, outages, rhs, tol=1e-12, max_iter=20000, *, plain=False, out=None, flows=None, island=True,
-              resid=True):
-        """gpcg_solve_contingencies (or gpcg_solve_plain): outages and rhs are
-        device tensors (int32[n_out], float64[n_bus]).  Returns the dict of
-        device output tensors x, flows, iters, status, island, resid."""
+              resid=True, noalloc=False):
+        """gpcg_solve_contingencies (gpcg_solve_plain with ``plain``,
+        gpcg_solve_contingencies_noalloc with ``noalloc``): outages and rhs
+        are device tensors (int32[n_out], float64[n_bus]).  Returns the dict
+        of device output tensors x, flows, iters, status, island, resid."""
         if flows is None:
             flows = self.kind == KIND_BP
         n_out = int(outages.shape[0])
         if out is None:
             out = self.alloc_outputs(n_out, flows, island, resid, outages.device)
-        fn = self._lib.gpcg_solve_plain if plain else self._lib.gpcg_solve_contingencies
+        fn = (self._lib.gpcg_solve_plain if plain else
+              self._lib.gpcg_solve_contingencies_noalloc if noalloc else self._lib.gpcg_solve_contingencies)
         _check(fn(self._h, n_out, _ptr(outages), _ptr(rhs), float(tol), int(max_iter), _ptr(out["x"]),
                   _ptr(out["flows"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["island"]),
                   _ptr(out["resid"])))

@@ -576,6 +576,7 @@ struct gpcg_context {
     bool timing = false, timed = false;
     int last_n_out = 0;
     bool last_ordered = false;
+    const int32_t *last_order = nullptr;  // device order of the last batched solve (context or fixed scratch)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     ~gpcg_context() {
@@ -664,9 +665,84 @@ struct gpcg_context {
 
 namespace {
 
+// Device memory one batched solve works in: the tiles' vectors, the
+// per-scenario re-dispatch factors and the buffers of the scenario ordering.
+struct Work {
+    double *ws = nullptr, *gfac = nullptr;
+    uint32_t *keys = nullptr, *keys_sorted = nullptr;
+    int32_t *iota = nullptr, *order = nullptr, *pos = nullptr;
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+};
+
+bool needs_order(int S_, int n_out) { return S_ > 1 && n_out > S_; }
+
+// The context's own workspace, grown on demand.
+Work context_work(gpcg_context *h, int n_out, int S_) {
+    h->ensure_workspace(n_out, S_);
+    Work w;
+    w.ws = h->ws.p;
+    w.gfac = h->gfac.p;
+    if (needs_order(S_, n_out)) {
+        if (h->keys.n < (size_t)n_out) {
+            h->keys.alloc(n_out);
+            h->keys_sorted.alloc(n_out);
+            h->iota.alloc(n_out);
+            h->order.alloc(n_out);
+            h->pos.alloc(n_out);
+        }
+        const size_t tb = gpcg::sort_temp_bytes(n_out);
+        if (h->sort_temp.n < tb) h->sort_temp.alloc(tb);
+        w.keys = h->keys.p;
+        w.keys_sorted = h->keys_sorted.p;
+        w.iota = h->iota.p;
+        w.order = h->order.p;
+        w.pos = h->pos.p;
+        w.temp = h->sort_temp.p;
+        w.temp_bytes = tb;
+    }
+    return w;
+}
+
+// The same buffers carved out of the library's fixed device scratch (no
+// allocation); fails when they do not fit.
+Work static_work(gpcg_context *h, int n_out, int S_) {
+    void *base = nullptr;
+    hip_check(gpcg::static_scratch(&base), "static scratch");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void *p = (char *)base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
+    Work w;
+    w.ws = (double *)take(tiles * gpcg::kVectors * gpcg::vec_stride(h->n_r, S_) * sizeof(double));
+    w.gfac = (double *)take((size_t)n_out * sizeof(double));
+    if (needs_order(S_, n_out)) {
+        w.keys = (uint32_t *)take((size_t)n_out * sizeof(uint32_t));
+        w.keys_sorted = (uint32_t *)take((size_t)n_out * sizeof(uint32_t));
+        w.iota = (int32_t *)take((size_t)n_out * sizeof(int32_t));
+        w.order = (int32_t *)take((size_t)n_out * sizeof(int32_t));
+        w.pos = (int32_t *)take((size_t)n_out * sizeof(int32_t));
+        w.temp_bytes = gpcg::sort_temp_bytes(n_out);
+        w.temp = take(w.temp_bytes);
+    }
+    if (off > gpcg::kStaticScratchBytes)
+        fail(GPCG_E_UNSUPPORTED, "the solve needs " + std::to_string(off >> 20) + " MiB of workspace, more than the " +
+                                     std::to_string(gpcg::kStaticScratchBytes >> 20) +
+                                     " MiB of the fixed scratch; solve fewer outages per call");
+    return w;
+}
+
+}  // namespace
+
+namespace {
+
 void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const double *rhs, double tol,
                int max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
-               uint8_t *island_out, double *resid_out, const double *rhs_cols = nullptr, int rhs_ld = 0) {
+               uint8_t *island_out, double *resid_out, const double *rhs_cols = nullptr, int rhs_ld = 0,
+               bool fixed_scratch = false) {
     if (!h) fail(GPCG_E_ARG, "context is NULL");
     if (n_out < 0) fail(GPCG_E_ARG, "n_out < 0");
     if (n_out == 0) return;
@@ -678,36 +754,31 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     if (!(tol >= 0.0) || !std::isfinite(tol)) fail(GPCG_E_ARG, "tol must be finite and >= 0");
     if (flows_out && h->kind != GPCG_KIND_BP) fail(GPCG_E_ARG, "flows are only defined for a B' context");
     hip_check(hipSetDevice(h->device), "hipSetDevice");
-    DevSchedule &D = h->schedule_for(S_);
-    h->ensure_workspace(n_out, S_);
+    if (fixed_scratch && S_ != h->S) fail(GPCG_E_ARG, "the fixed-scratch solve runs at the context's block");
+    DevSchedule &D = h->schedule_for(S_);  // built at setup for the context's block
+    const Work w = fixed_scratch ? static_work(h, n_out, S_) : context_work(h, n_out, S_);
     // residual of the base state for this right-hand side, in double-double
     if (!rhs_cols)
         hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
                                              h->rho_b.p, h->stream),
                   "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
+    p.ws = w.ws;
+    p.gfac_out = w.gfac;
     p.rhs_cols = rhs_cols;
     p.rhs_ld = rhs_ld;
     p.zero_start = (!rhs_cols && h->zero_start) ? 1 : 0;
     const int32_t *pos = nullptr;
-    if (S_ > 1 && n_out > S_) {
+    if (needs_order(S_, n_out)) {
         // group scenarios of similar expected work into the same tiles
-        if (h->keys.n < (size_t)n_out) {
-            h->keys.alloc(n_out);
-            h->keys_sorted.alloc(n_out);
-            h->iota.alloc(n_out);
-            h->order.alloc(n_out);
-            h->pos.alloc(n_out);
-        }
-        const size_t tb = gpcg::sort_temp_bytes(n_out);
-        if (h->sort_temp.n < tb) h->sort_temp.alloc(tb);
         hip_check(gpcg::launch_order(n_out, outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
-                                     h->isl_hi.p, h->theta_b.p, h->keys.p, h->keys_sorted.p, h->iota.p, h->order.p,
-                                     h->pos.p, h->sort_temp.p, tb, h->stream),
+                                     h->isl_hi.p, h->theta_b.p, w.keys, w.keys_sorted, w.iota, w.order, w.pos, w.temp,
+                                     w.temp_bytes, h->stream),
                   "scenario ordering");
-        p.order = h->order.p;
-        pos = h->pos.p;
+        p.order = w.order;
+        pos = w.pos;
     }
+    h->last_order = w.order;
     h->last_n_out = n_out;
     h->last_ordered = pos != nullptr;
     const int ring = D.ring_max();
@@ -750,9 +821,9 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.add_base = (!rhs_cols && !h->zero_start) ? 1 : 0;
     o.outages = outages;
     o.pos = pos;
-    o.ws = h->ws.p;
+    o.ws = w.ws;
     o.status = status_out;
-    o.gfac = h->gfac.p;
+    o.gfac = w.gfac;
     o.x_out = x_out;
     o.flows_out = flows_out;
     o.resid_out = resid_out;
@@ -1145,6 +1216,10 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
 
         auto h = std::make_unique<gpcg_context>();
         hip_check(hipGetDevice(&h->device), "hipGetDevice");
+        {  // the fixed scratch's address on this device (looked up once per device)
+            void *fixed = nullptr;
+            hip_check(gpcg::static_scratch(&fixed), "static scratch");
+        }
         h->stream = (hipStream_t)stream;
         h->n_bus = n_bus;
         h->m = m;
@@ -1281,6 +1356,16 @@ int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, co
         if (!h) fail(GPCG_E_ARG, "context is NULL");
         run_solve(h, h->S, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
                   resid_out);
+    });
+}
+
+int gpcg_solve_contingencies_noalloc(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
+                                     int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out,
+                                     int32_t *status_out, uint8_t *island_out, double *resid_out) {
+    return guarded([&] {
+        if (!h) fail(GPCG_E_ARG, "context is NULL");
+        run_solve(h, h->S, n_out, outages, rhs, tol, max_iter, x_out, flows_out, iters_out, status_out, island_out,
+                  resid_out, nullptr, 0, true);
     });
 }
 
@@ -1575,7 +1660,7 @@ int gpcg_get_order(gpcg_t h, int32_t n_out, int32_t *order) {
         if (!h || !order) fail(GPCG_E_ARG, "NULL argument");
         if (n_out != h->last_n_out) fail(GPCG_E_ARG, "n_out differs from the last solve");
         if (h->last_ordered) {
-            hip_check(hipMemcpyAsync(order, h->order.p, (size_t)n_out * sizeof(int32_t), hipMemcpyDeviceToHost,
+            hip_check(hipMemcpyAsync(order, h->last_order, (size_t)n_out * sizeof(int32_t), hipMemcpyDeviceToHost,
                                      h->stream),
                       "copy");
             hip_check(hipStreamSynchronize(h->stream), "sync");

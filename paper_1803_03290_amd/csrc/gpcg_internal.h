@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gpcg.h"
+
 namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
@@ -221,6 +223,14 @@ hipError_t launch_screen(int n_out, int m, const double *flows, const double *F,
 // out[j] = sum_r w[r] a[r * lda + j]
 hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda, const double *w, double *out,
                                 hipStream_t st);
+
+// The library's fixed device scratch: a file-scope device array of
+// kStaticScratchBytes on every GPU the library runs on, for the solve entry
+// point that allocates nothing.  static_scratch() returns its address on the
+// current device, looked up with hipGetSymbolAddress once per device and
+// kept (the array's name is not a device address in host code).
+constexpr size_t kStaticScratchBytes = GPCG_NOALLOC_SCRATCH_BYTES;
+hipError_t static_scratch(void **ptr);
 
 // Order scenarios by expected PCG work so that a tile's columns stop at
 // about the same iteration: non-islanding outages first, then islanding

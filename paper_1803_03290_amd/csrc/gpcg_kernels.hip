@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <climits>
 #include <hipcub/hipcub.hpp>
+#include <mutex>
 #include <type_traits>
 
 namespace gpcg {
@@ -677,6 +678,30 @@ __global__ void order_inverse_kernel(int n, const int32_t *order, int32_t *pos) 
 }
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free solve.  Each GPU holds its own
+// copy until the process ends; every call on a GPU shares it.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 size_t sort_temp_bytes(int n) {
     size_t bytes = 0;
