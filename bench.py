@@ -14,7 +14,7 @@ Besides the contract fields the line carries:
     its average launch time (HIP events on the context's stream), against
     the 8 TB/s HBM3E peak.  The bytes are the method's own work: 120 bytes
     per row per scenario per iteration of that scenario (15 vector passes),
-    the matrix and factor entries once per tile per iteration of the tile,
+    the matrix and factor entries once per wavefront per iteration it runs,
     and init and output passes; sweeps of columns that have already stopped
     are not counted (their share is reported as "idle_column_overhead").
     "traffic" comes from the committed rocprofv3 counter summary when it was
@@ -51,13 +51,14 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_tile.hip")
 VEC_BYTES_PER_ROW_ITER = 120.0
 
 
-def own_work_bytes(info: dict, scen_iters, tile_iters, m: int) -> float:
+def own_work_bytes(info: dict, scen_iters, wave_iters: int, m: int) -> float:
     """Algorithmic bytes of one solve: every scenario's own iterations for
-    the vectors, every tile's iterations for the shared matrix entries."""
+    the vectors, every wavefront iteration for the shared matrix entries
+    (read once per iteration for the wave's S columns)."""
     nr = info["n_r"]
     vec = VEC_BYTES_PER_ROW_ITER * nr * float(sum(int(k) for k in scen_iters))
     mat_iter = 12.0 * (info["nnz_a"] + info["nnz_l"] + info["nnz_u"]) + 12.0 * (nr + 1)
-    mat = mat_iter * float(sum(int(k) for k in tile_iters))
+    mat = mat_iter * float(wave_iters)
     io = (6.0 * 8.0 * nr + 8.0 * m) * len(scen_iters)
     return vec + mat + io
 
@@ -505,12 +506,10 @@ def main():
     status = out["status"].cpu().numpy()
     resid = out["resid"].cpu().numpy()
     S = info["block"]
-    n_tiles = (m + S - 1) // S
-    it_tiles = iters[ctx.order(m)]  # iterations in tile order
-    tile_K = [int(it_tiles[t * S:(t + 1) * S].max()) for t in range(n_tiles)]
-    algo_bytes = own_work_bytes(info, iters, tile_K, m)
+    waves, wave_iters = ctx.sweeps()  # persistent wavefronts and their iterations, last solve
+    algo_bytes = own_work_bytes(info, iters, wave_iters, m)
     achieved = algo_bytes / (pcg_ms * 1e-3) / 1e9
-    idle_overhead = float(S * sum(tile_K)) / max(1, int(iters.sum()))
+    idle_overhead = float(S * wave_iters) / max(1, int(iters.sum()))
     progress(f"headline: {m / (ms_step * 1e-3):.0f} scenarios/s, pcg kernel {pcg_ms:.1f} ms")
 
     alt = None
@@ -592,9 +591,9 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": f"pcg_tile_kernel<{S}>", "algorithmic_bytes_per_launch": algo_bytes,
+            "kernel": f"pcg_wave_kernel<{S}>", "algorithmic_bytes_per_launch": algo_bytes,
             "avg_launch_ms": pcg_ms, "kernel_digest": kernel_digest(), "idle_column_overhead": idle_overhead,
-            "bytes": "120 B per row per scenario-iteration + 12 B per matrix/factor entry per tile-iteration + "
+            "bytes": "120 B per row per scenario-iteration + 12 B per matrix/factor entry per wave-iteration + "
                      "init/output; stopped columns not counted",
         },
         "spmm": spmm,
@@ -607,7 +606,7 @@ def main():
             "status_counts": st_counts,
             "max_true_rel_residual": float(resid.max()),
             "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
-            "tile_iters_sum": int(sum(tile_K)), "scenario_iters_sum": int(iters.sum()),
+            "waves": waves, "wave_iters_sum": int(wave_iters), "scenario_iters_sum": int(iters.sum()),
             "bridges": info["n_bridges"], "setup_s": setup_s, "base_iters": info["base_iters"],
             "base_resid": info["base_resid"],
         },

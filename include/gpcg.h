@@ -211,8 +211,11 @@ int gpcg_get_base(gpcg_t h, uint8_t *is_bridge, double *theta_base);
  *   resid_out:  device f64[n_out] or NULL: true relative residual
  *               ||rhs'_M - A_c theta_M|| / ||rhs'_M|| of the returned
  *               theta, formed in double-double.
- * Workspace (5 n_r S doubles per tile) is owned by the context and grows on
- * demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
+ * The scenarios are handed out by an atomic queue to persistent wavefronts
+ * (as many as fit the device at once, at most one per S scenarios), each
+ * with S scenario columns; a column that stops writes its results and takes
+ * the next scenario, heaviest expected work first.  Workspace (4 (n_r + 1)
+ * S doubles per wavefront) is owned by the context and grows on demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
  * max_iter < 1, or flows requested from a B'' context.  Outage ids are read
  * on the device only: an id outside [-1, m) gives that scenario status
  * GPCG_BAD_OUTAGE and zero outputs, the other scenarios are unaffected.
@@ -225,14 +228,18 @@ int gpcg_solve_contingencies(gpcg_t h, int32_t n_out, const int32_t *outages, co
  * gpcg_solve_contingencies without any device allocation, for callers that
  * cannot allocate: code under HIP graph capture, tight serving loops and
  * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
- * gpcg_solve_contingencies (bit for bit); its workspace (the tiles' vectors,
- * 4 (n_r + 1) S doubles per tile of S scenarios, the re-dispatch factors and
- * the scenario ordering's buffers) is carved from a fixed device array of
- * GPCG_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
- * until the process ends, instead of the context's own growable workspace.
- *   Limit: a call whose workspace exceeds that size fails with
- *   GPCG_E_UNSUPPORTED before anything is enqueued (about 1,000 outages of a
- *   2,000-bus grid at block 4 fit; split larger lists into several calls).
+ * gpcg_solve_contingencies (bit for bit); its workspace (the re-dispatch
+ * factors and the scenario ordering's buffers, about 28 bytes per scenario,
+ * then the wavefronts' vectors, 4 (n_r + 1) S doubles each) is carved from
+ * a fixed device array of GPCG_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends, instead of the context's
+ * own growable workspace.  When fewer wavefronts fit than the ordinary
+ * solve would run, fewer run (e.g. 255 instead of 700 for the 2,000-bus
+ * grid at block 4), each taking more scenarios from the queue.
+ *   Limit: a call whose per-scenario buffers and one wavefront's vectors do
+ *   not fit fails with GPCG_E_UNSUPPORTED before anything is enqueued (more
+ *   than about two million scenarios, or a grid of more than about 30,000
+ *   buses at block 64; split the list, or use a smaller block).
  *   Sharing: every call on one GPU uses the same array, from any context, and
  *   the array keeps the last call's contents (nothing in it needs to start at
  *   zero).  Calls that overlap on one GPU (on different streams or threads)
@@ -395,10 +402,10 @@ int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, co
 
 /*
  * The same computation with the plain per-scenario PCG: one scenario at a
- * time (S = 1), each as its own launch in the context's stream, with the
- * wavefront's 64 lanes spread over rows instead of scenarios.  Same
- * arguments and results as gpcg_solve_contingencies; this is the baseline
- * the batched form is measured against.
+ * time (S = 1): a single wavefront takes the scenarios one after the other,
+ * with its 64 lanes spread over rows instead of scenarios.  Same arguments
+ * and results as gpcg_solve_contingencies; this is the baseline the batched
+ * form is measured against.
  */
 int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const double *rhs, double tol,
                      int32_t max_iter, double *x_out, double *flows_out, int32_t *iters_out, int32_t *status_out,
@@ -417,14 +424,22 @@ int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const doub
 int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, double *q, double *pq);
 
 /*
- * Tile order of the last gpcg_solve_contingencies call: order[j] is the
- * scenario solved in tile position j (tile j / S, column j % S).  Scenarios
- * are grouped by expected work (non-islanding first, then islanding, each by
- * the base-case flow of the outaged branch) so that the columns of a tile
- * stop at about the same iteration.  order: host int32[n_out] (n_out of that
- * call).  Synchronises the context's stream.
+ * Queue order of the last batched solve: order[j] is the scenario the queue
+ * handed out j-th.  Scenarios are ranked by expected work (islanding
+ * outages, then the base-case flow of the outaged branch) and handed out
+ * from the heaviest, so that the last ones to finish are short.  order:
+ * host int32[n_out] (n_out of that call).  Synchronises the context's
+ * stream.
  */
 int gpcg_get_order(gpcg_t h, int32_t n_out, int32_t *order);
+
+/*
+ * Work of the last solve's PCG launch, for roofline accounting: *waves =
+ * the persistent wavefronts it ran, *wave_iterations = the PCG iterations
+ * summed over them (each wavefront iteration sweeps the matrix and factor
+ * entries once for its S columns).  Synchronises the context's stream.
+ */
+int gpcg_get_sweeps(gpcg_t h, int32_t *waves, int64_t *wave_iterations);
 
 /*
  * Kernel timing.  With timing enabled, every solve records a HIP event on

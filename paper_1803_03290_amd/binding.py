@@ -80,6 +80,7 @@ SIGNATURES = {
                             _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "gpcg_get_order": (C.c_int, [_VP, C.c_int32, _i32p]),
+    "gpcg_get_sweeps": (C.c_int, [_VP, _i32p, C.POINTER(C.c_int64)]),
     "gpcg_set_timing": (C.c_int, [_VP, C.c_int]),
     "gpcg_get_timing": (C.c_int, [_VP, _f64p]),
 }
@@ -383,10 +384,17 @@ class Context:
         return out
 
     def order(self, n_out) -> np.ndarray:
-        """gpcg_get_order: scenario per tile position of the last batched solve."""
+        """gpcg_get_order: scenario handed out j-th by the last solve's queue."""
         o = np.zeros(n_out, np.int32)
         _check(self._lib.gpcg_get_order(self._h, int(n_out), _ip(o)))
         return o
+
+    def sweeps(self):
+        """gpcg_get_sweeps: (waves, PCG iterations summed over the waves) of
+        the last solve's launch."""
+        w, n = C.c_int32(0), C.c_int64(0)
+        _check(self._lib.gpcg_get_sweeps(self._h, C.byref(w), C.byref(n)))
+        return int(w.value), int(n.value)
 
     def set_timing(self, enable=True):
         """gpcg_set_timing: bracket every solve's PCG kernels with HIP events."""

@@ -553,6 +553,10 @@ struct gpcg_context {
     DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
+    DevBuf<int32_t> queue;               // the PCG launch's queue counter
+    DevBuf<unsigned long long> sweeps;   // iterations summed over the waves of the last launch
+    int last_waves = 0;                  // waves of the last PCG launch
+    int max_waves[7] = {0, 0, 0, 0, 0, 0, 0};  // wavefronts that fit the device at once, per log2(block)
     DevBuf<int32_t> inc_ptr, inc_br;  // branches at each bus
     DevBuf<double> ov_theta, ov_flows, ov_g, ov_lambda;  // overload-gradient workspace
     DevBuf<double> diag_bus;                             // diagonal of A by bus (slack 0), built on first use
@@ -645,29 +649,39 @@ struct gpcg_context {
         p.rhs = rhs;
         p.outages = outages;
         p.n_out = n_out;
-        p.tile0 = 0;
         p.tol2 = tol * tol;
         p.max_iter = max_iter;
-        p.ws = ws.p;
+        p.queue = queue.p;
+        p.sweeps = sweeps.p;
         p.iters_out = iters;
         p.status_out = status;
-        p.gfac_out = gfac.p;
         return p;
     }
 
-    void ensure_workspace(int n_out, int S_) {
-        const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
-        const size_t need = tiles * gpcg::kVectors * gpcg::vec_stride(n_r, S_);
-        if (ws.n < need) ws.alloc(need);
-        if (gfac.n < (size_t)std::max(n_out, 1)) gfac.alloc(std::max(n_out, 1));
+    // Persistent wavefronts of a launch at block S_: one scenario at a time
+    // for the plain form (S_ = 1), else as many as fit the device at once,
+    // but no more than the scenarios need.
+    int waves_for(int S_, int n_out, const DevSchedule &D) {
+        if (S_ == 1) return 1;
+        int lg = 0;
+        while ((1 << lg) < S_) ++lg;
+        if (!max_waves[lg]) {
+            max_waves[lg] = gpcg::pcg_max_waves(S_, D.ring_max());
+            if (max_waves[lg] <= 0) fail(GPCG_E_HIP, "occupancy query of the PCG kernel failed");
+        }
+        return std::max(1, std::min(max_waves[lg], (n_out + S_ - 1) / S_));
     }
+
+    size_t ws_slot(int S_) const { return (size_t)gpcg::kVectors * gpcg::vec_stride(n_r, S_); }
 };
 
 namespace {
 
-// Device memory one batched solve works in: the tiles' vectors, the
+// Device memory one batched solve works in: the waves' vectors, the
 // per-scenario re-dispatch factors and the buffers of the scenario ordering.
 struct Work {
+    int n_waves = 0;
+    size_t ws_slot = 0;
     double *ws = nullptr, *gfac = nullptr;
     uint32_t *keys = nullptr, *keys_sorted = nullptr;
     int32_t *iota = nullptr, *order = nullptr, *pos = nullptr;
@@ -678,9 +692,12 @@ struct Work {
 bool needs_order(int S_, int n_out) { return S_ > 1 && n_out > S_; }
 
 // The context's own workspace, grown on demand.
-Work context_work(gpcg_context *h, int n_out, int S_) {
-    h->ensure_workspace(n_out, S_);
+Work context_work(gpcg_context *h, int n_out, int S_, const DevSchedule &D) {
     Work w;
+    w.n_waves = h->waves_for(S_, n_out, D);
+    w.ws_slot = h->ws_slot(S_);
+    if (h->ws.n < (size_t)w.n_waves * w.ws_slot) h->ws.alloc((size_t)w.n_waves * w.ws_slot);
+    if (h->gfac.n < (size_t)std::max(n_out, 1)) h->gfac.alloc(std::max(n_out, 1));
     w.ws = h->ws.p;
     w.gfac = h->gfac.p;
     if (needs_order(S_, n_out)) {
@@ -705,8 +722,10 @@ Work context_work(gpcg_context *h, int n_out, int S_) {
 }
 
 // The same buffers carved out of the library's fixed device scratch (no
-// allocation); fails when they do not fit.
-Work static_work(gpcg_context *h, int n_out, int S_) {
+// allocation): the per-scenario buffers first, then as many wave slots as
+// the rest holds (at most what the launch would use).  Fails when not even
+// one wave slot fits.
+Work static_work(gpcg_context *h, int n_out, int S_, const DevSchedule &D) {
     void *base = nullptr;
     hip_check(gpcg::static_scratch(&base), "static scratch");
     size_t off = 0;
@@ -715,9 +734,7 @@ Work static_work(gpcg_context *h, int n_out, int S_) {
         off += (bytes + 255) / 256 * 256;
         return p;
     };
-    const size_t tiles = (size_t)((n_out + S_ - 1) / S_);
     Work w;
-    w.ws = (double *)take(tiles * gpcg::kVectors * gpcg::vec_stride(h->n_r, S_) * sizeof(double));
     w.gfac = (double *)take((size_t)n_out * sizeof(double));
     if (needs_order(S_, n_out)) {
         w.keys = (uint32_t *)take((size_t)n_out * sizeof(uint32_t));
@@ -728,10 +745,16 @@ Work static_work(gpcg_context *h, int n_out, int S_) {
         w.temp_bytes = gpcg::sort_temp_bytes(n_out);
         w.temp = take(w.temp_bytes);
     }
-    if (off > gpcg::kStaticScratchBytes)
-        fail(GPCG_E_UNSUPPORTED, "the solve needs " + std::to_string(off >> 20) + " MiB of workspace, more than the " +
-                                     std::to_string(gpcg::kStaticScratchBytes >> 20) +
-                                     " MiB of the fixed scratch; solve fewer outages per call");
+    w.ws_slot = h->ws_slot(S_);
+    const size_t slot_bytes = w.ws_slot * sizeof(double);
+    const size_t room = off < gpcg::kStaticScratchBytes ? gpcg::kStaticScratchBytes - off : 0;
+    const int fit = (int)std::min<size_t>(room / slot_bytes, (size_t)1 << 30);
+    if (fit < 1)
+        fail(GPCG_E_UNSUPPORTED, "the solve needs more than the " + std::to_string(gpcg::kStaticScratchBytes >> 20) +
+                                     " MiB of the fixed scratch (" + std::to_string((off + slot_bytes) >> 20) +
+                                     " MiB for one wavefront); solve fewer outages per call");
+    w.n_waves = std::min(fit, h->waves_for(S_, n_out, D));
+    w.ws = (double *)take((size_t)w.n_waves * slot_bytes);
     return w;
 }
 
@@ -756,7 +779,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     hip_check(hipSetDevice(h->device), "hipSetDevice");
     if (fixed_scratch && S_ != h->S) fail(GPCG_E_ARG, "the fixed-scratch solve runs at the context's block");
     DevSchedule &D = h->schedule_for(S_);  // built at setup for the context's block
-    const Work w = fixed_scratch ? static_work(h, n_out, S_) : context_work(h, n_out, S_);
+    const Work w = fixed_scratch ? static_work(h, n_out, S_, D) : context_work(h, n_out, S_, D);
     // residual of the base state for this right-hand side, in double-double
     if (!rhs_cols)
         hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
@@ -764,35 +787,27 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
                   "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
     p.ws = w.ws;
+    p.ws_slot = w.ws_slot;
     p.gfac_out = w.gfac;
+    p.x_out = x_out;
     p.rhs_cols = rhs_cols;
     p.rhs_ld = rhs_ld;
     p.zero_start = (!rhs_cols && h->zero_start) ? 1 : 0;
-    const int32_t *pos = nullptr;
+    p.add_base = (!rhs_cols && !h->zero_start) ? 1 : 0;
     if (needs_order(S_, n_out)) {
-        // group scenarios of similar expected work into the same tiles
+        // the queue hands out the scenarios of most expected work first
         hip_check(gpcg::launch_order(n_out, outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
                                      h->isl_hi.p, h->theta_b.p, w.keys, w.keys_sorted, w.iota, w.order, w.pos, w.temp,
                                      w.temp_bytes, h->stream),
                   "scenario ordering");
         p.order = w.order;
-        pos = w.pos;
     }
-    h->last_order = w.order;
+    h->last_order = p.order;
     h->last_n_out = n_out;
-    h->last_ordered = pos != nullptr;
-    const int ring = D.ring_max();
-    const int n_tiles = (n_out + S_ - 1) / S_;
+    h->last_ordered = p.order != nullptr;
+    h->last_waves = w.n_waves;
     if (h->timing) hip_check(hipEventRecord(h->ev0, h->stream), "event");
-    if (S_ == 1) {
-        // plain: one scenario per launch, one after the other
-        for (int t = 0; t < n_tiles; ++t) {
-            p.tile0 = t;
-            hip_check(gpcg::launch_pcg(p, 1, 1, ring, h->stream), "pcg launch");
-        }
-    } else {
-        hip_check(gpcg::launch_pcg(p, S_, n_tiles, ring, h->stream), "pcg launch");
-    }
+    hip_check(gpcg::launch_pcg(p, S_, w.n_waves, D.ring_max(), h->stream), "pcg launch");
     if (h->timing) {
         hip_check(hipEventRecord(h->ev1, h->stream), "event");
         h->timed = true;
@@ -802,7 +817,6 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.n_bus = h->n_bus;
     o.m = h->m;
     o.kind = h->kind;
-    o.S = S_;
     o.n_out = n_out;
     o.a_rowptr = h->a_rowptr.p;
     o.a_col = h->a_col.p;
@@ -820,8 +834,6 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.rhs_ld = rhs_ld;
     o.add_base = (!rhs_cols && !h->zero_start) ? 1 : 0;
     o.outages = outages;
-    o.pos = pos;
-    o.ws = w.ws;
     o.status = status_out;
     o.gfac = w.gfac;
     o.x_out = x_out;
@@ -857,7 +869,9 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
     DevBuf<double> rho_bus;  // rho in bus numbering (entry 0, the slack, is 0)
     rho_bus.upload(zero.data(), n_bus, h->stream);
     DevSchedule &D = h->schedule_for(1);
-    h->ensure_workspace(1, 1);
+    const Work w = context_work(h, 1, 1, D);
+    DevBuf<double> xb;  // each pass's correction, by bus
+    xb.alloc(n_bus);
     double bnorm2 = 0.0;
     hip_check(gpcg::launch_sumsq(n_bus - 1, rhs.p + 1, dsum.p + 1, h->stream), "sumsq");
     hip_check(hipMemcpyAsync(&bnorm2, dsum.p + 1, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy");
@@ -882,8 +896,13 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
         gpcg::PcgParams p = h->params(D, out1.p, 1, rhs.p, 1e-13, max_iter, it.p, st.p);
         p.rhs_cols = rho_bus.p;
         p.rhs_ld = n_bus;
+        p.ws = w.ws;
+        p.ws_slot = w.ws_slot;
+        p.gfac_out = w.gfac;
+        p.x_out = xb.p;
+        p.add_base = 0;
         hip_check(gpcg::launch_pcg(p, 1, 1, D.ring_max(), h->stream), "base pcg");
-        hip_check(gpcg::launch_base_accumulate(h->n_r, h->theta_b.p, h->ws.p, h->stream), "base accumulate");
+        hip_check(gpcg::launch_base_accumulate(n_bus, h->theta_b.p, xb.p, h->stream), "base accumulate");
         int its = 0;
         hip_check(hipMemcpyAsync(&its, it.p, sizeof(int), hipMemcpyDeviceToHost, h->stream), "copy");
         hip_check(hipStreamSynchronize(h->stream), "sync");
@@ -912,7 +931,7 @@ struct BatchGrid {
     const double *rhs = nullptr;
     double *x_out = nullptr, *flows_out = nullptr, *resid_out = nullptr;
     int32_t *iters_out = nullptr, *status_out = nullptr;
-    DevBuf<double> ws, rho_b, gfac;
+    DevBuf<double> rho_b, gfac;
     DevBuf<int32_t> order, pos;
 };
 
@@ -932,12 +951,14 @@ struct BatchSpec {
 }  // namespace
 
 struct gpcg_batch {
-    int device = 0, S = 1, ring = 1, total_tiles = 0, max_iter = 1;
+    int device = 0, S = 1, ring = 1, n_waves = 0, max_iter = 1;
     double tol = 0.0;
     hipStream_t stream = nullptr;
     std::vector<std::unique_ptr<BatchGrid>> g;  // heaviest grid first
     DevBuf<gpcg::PcgParams> params;
-    DevBuf<int32_t> tile_start;
+    DevBuf<double> ws;                  // the waves' slots, sized for the largest grid
+    DevBuf<int32_t> queues;             // one queue counter per grid
+    DevBuf<unsigned long long> sweeps;  // iterations summed over the waves
     hipStream_t outer = nullptr;  // the contexts' stream; the batch works on a stream of its own
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
@@ -1005,22 +1026,40 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
                      [](const std::unique_ptr<BatchGrid> &x, const std::unique_ptr<BatchGrid> &y) {
                          return x->ctx->n_r > y->ctx->n_r;
                      });
-    std::vector<gpcg::PcgParams> prm;
-    std::vector<int32_t> start(1, 0);
+    // schedules, ring and workspace slot of the largest grid, wave count
+    size_t slot = 0;
+    long columns = 0;
     for (auto &G : b->g) {
         gpcg_context *h = G->ctx;
         h->schedule_for(S);
         G->sched = (S == 1) ? h->sched_plain : h->sched_batched;
         b->ring = std::max(b->ring, G->sched->ring_max());
-        G->ws.alloc(std::max<size_t>(1, (size_t)G->tiles * gpcg::kVectors * gpcg::vec_stride(h->n_r, S)));
+        slot = std::max(slot, h->ws_slot(S));
+        columns += G->tiles;
+    }
+    const int cap = S == 1 ? 1 : gpcg::pcg_max_waves(S, b->ring);
+    if (cap <= 0) fail(GPCG_E_HIP, "occupancy query of the PCG kernel failed");
+    b->n_waves = (int)std::max<long>(1, std::min<long>(cap, columns));
+    b->ws.alloc((size_t)b->n_waves * slot);
+    b->queues.alloc(b->g.size());
+    b->sweeps.alloc(1);
+    std::vector<gpcg::PcgParams> prm;
+    int gi = 0;
+    for (auto &G : b->g) {
+        gpcg_context *h = G->ctx;
         G->rho_b.alloc(h->n_r);
         G->gfac.alloc(std::max(G->n_out, 1));
         gpcg::PcgParams p = h->params(*G->sched, G->outages, G->n_out, G->rhs, tol, max_iter, G->iters_out,
                                       G->status_out);
-        p.ws = G->ws.p;
+        p.ws = b->ws.p;
+        p.ws_slot = slot;
+        p.queue = b->queues.p + gi++;
+        p.sweeps = b->sweeps.p;
         p.rho_b = G->rho_b.p;
         p.gfac_out = G->gfac.p;
+        p.x_out = G->x_out;
         p.zero_start = h->zero_start;
+        p.add_base = h->zero_start ? 0 : 1;
         if (S > 1 && G->n_out > S) {
             const int n = G->n_out;
             DevBuf<uint32_t> keys, keys_sorted;
@@ -1041,11 +1080,8 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
             p.order = G->order.p;
         }
         prm.push_back(p);
-        start.push_back(start.back() + G->tiles);
     }
-    b->total_tiles = start.back();
     b->params.upload(prm.data(), prm.size(), b->stream);
-    b->tile_start.upload(start.data(), start.size(), b->stream);
     hip_check(hipStreamSynchronize(b->stream), "batch upload");
     return b;
 }
@@ -1060,8 +1096,7 @@ void batch_enqueue(gpcg_batch *b) {
                                              G->rho_b.p, b->stream),
                   "base residual");
     }
-    hip_check(gpcg::launch_pcg_multi(b->params.p, b->tile_start.p, (int)b->g.size(), b->S, b->total_tiles, b->ring,
-                                     b->stream),
+    hip_check(gpcg::launch_pcg_multi(b->params.p, (int)b->g.size(), b->S, b->n_waves, b->ring, b->stream),
               "batch launch");
     for (auto &G : b->g) {
         gpcg_context *h = G->ctx;
@@ -1071,7 +1106,6 @@ void batch_enqueue(gpcg_batch *b) {
         o.n_bus = h->n_bus;
         o.m = h->m;
         o.kind = h->kind;
-        o.S = b->S;
         o.n_out = G->n_out;
         o.a_rowptr = h->a_rowptr.p;
         o.a_col = h->a_col.p;
@@ -1087,8 +1121,6 @@ void batch_enqueue(gpcg_batch *b) {
         o.rhs = G->rhs;
         o.add_base = h->zero_start ? 0 : 1;
         o.outages = G->outages;
-        o.pos = G->order.p ? G->pos.p : nullptr;
-        o.ws = G->ws.p;
         o.status = G->status_out;
         o.gfac = G->gfac.p;
         o.x_out = G->x_out;
@@ -1291,6 +1323,8 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
             h->inc_br.upload(br.data(), br.size(), st);
         }
         h->rho_b.alloc(nr);
+        h->queue.alloc(1);
+        h->sweeps.alloc(1);
         hip_check(hipStreamSynchronize(st), "setup upload");
         h->schedule_for(S);
         if (theta_base) {
@@ -1660,13 +1694,26 @@ int gpcg_get_order(gpcg_t h, int32_t n_out, int32_t *order) {
         if (!h || !order) fail(GPCG_E_ARG, "NULL argument");
         if (n_out != h->last_n_out) fail(GPCG_E_ARG, "n_out differs from the last solve");
         if (h->last_ordered) {
-            hip_check(hipMemcpyAsync(order, h->last_order, (size_t)n_out * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                     h->stream),
+            std::vector<int32_t> sorted(n_out);
+            hip_check(hipMemcpyAsync(sorted.data(), h->last_order, (size_t)n_out * sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, h->stream),
                       "copy");
             hip_check(hipStreamSynchronize(h->stream), "sync");
+            for (int j = 0; j < n_out; ++j) order[j] = sorted[n_out - 1 - j];  // taken from the heavy end
         } else {
             for (int j = 0; j < n_out; ++j) order[j] = j;
         }
+    });
+}
+
+int gpcg_get_sweeps(gpcg_t h, int32_t *waves, int64_t *wave_iterations) {
+    return guarded([&] {
+        if (!h || !waves || !wave_iterations) fail(GPCG_E_ARG, "NULL argument");
+        unsigned long long n = 0;
+        hip_check(hipMemcpyAsync(&n, h->sweeps.p, sizeof(n), hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        *waves = h->last_waves;
+        *wave_iterations = (int64_t)n;
     });
 }
 

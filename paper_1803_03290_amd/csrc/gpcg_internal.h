@@ -65,8 +65,8 @@ constexpr int kBwdRowBits = 20;                      // row and pre-order fields
 constexpr int kBwdRowMask = (1 << kBwdRowBits) - 1;  // also the "none" pre-order number
 constexpr int kBwdMaxRing = 2048;                    // ring rows of the backward solve (slot + 2 < 2^12)
 
-// Everything one launch of the tile kernel needs.  All pointers are device
-// memory.  Reduced row i is bus i + 1.
+// Everything one launch of the persistent PCG kernel needs.  All pointers
+// are device memory.  Reduced row i is bus i + 1.
 struct PcgParams {
     int n_r, n_bus, m, kind;
     Program fwd;   // y = L^-1 r  (rows in a dependency-respecting order)
@@ -88,20 +88,31 @@ struct PcgParams {
     const double *rhs_cols;
     int rhs_ld;
     int zero_start;  // 1: start from x = 0 (r0 = P'_M), the result is theta itself
-    // scenarios: tile position j solves scenario order[j] (NULL: j itself)
+    // scenarios: queue position j takes scenario order[n_out - 1 - j] (the
+    // order sorted by expected work, taken from its heavy end; NULL: j)
     const int32_t *outages;
     const int32_t *order;
     int n_out;
-    int tile0;  // first tile of this launch (plain mode launches one tile at a time)
+    int32_t *queue;                // next queue position (zeroed before the launch)
+    unsigned long long *sweeps;    // NULL, or the sum over waves of the iterations each ran
     double tol2;
     int max_iter;
-    double *ws;  // tiles x kVectors x (n_r + 1) rows x S: pairs {delta, p}, pairs {r, w}
+    // workspace: wave w owns ws + w * ws_slot: pairs {delta, p}, pairs {r, w},
+    // kVectors x (n_r + 1) rows x S
+    double *ws;
+    size_t ws_slot;
+    // results, written when a column stops: x = (theta_b if add_base) + delta
+    // on the main system [n_out x n_bus], steps, status, re-dispatch factor
+    double *x_out;
+    int add_base;
     int32_t *iters_out, *status_out;
-    double *gfac_out;  // per scenario: re-dispatch factor dP / S_gen (0 when none)
+    double *gfac_out;
 };
 
+// Outputs formed after the PCG launch from the angles it wrote: island
+// flags, flows, true residuals.
 struct OutParams {
-    int n_r, n_bus, m, kind, S, n_out;
+    int n_r, n_bus, m, kind, n_out;
     const int32_t *a_rowptr, *a_col;
     const double *a_val;
     const int32_t *br_from, *br_to;
@@ -113,11 +124,10 @@ struct OutParams {
     int rhs_ld;
     int add_base;  // 1: x = theta_b + delta (warm start from the base state)
     const int32_t *outages;
-    const int32_t *pos;  // tile position of each scenario (NULL: the scenario index)
-    const double *ws;
     const int32_t *status;
     const double *gfac;
-    double *x_out, *flows_out, *resid_out;
+    const double *x_out;
+    double *flows_out, *resid_out;
     uint8_t *island_out;
 };
 
@@ -186,16 +196,19 @@ struct FdpfParams {
 
 // Launchers (launch_pcg in gpcg_tile.hip, the rest in gpcg_kernels.hip).  They
 // return hipSuccess or the launch error.
-hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st);
-// several grids in one launch: grids[g] (device) solves tiles
-// [tile_start[g], tile_start[g + 1]) of the launch (tile_start device,
-// n_grids + 1 entries); ring_rows = the largest ring of any grid
-hipError_t launch_pcg_multi(const PcgParams *grids, const int *tile_start, int n_grids, int S, int n_tiles,
-                            int ring_rows, hipStream_t st);
+// n_waves persistent wavefronts (each with a workspace slot) over one queue;
+// the queue and sweep counters are reset by a kernel launched first.
+hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, hipStream_t st);
+// several grids in one launch: grids (device, n_grids entries, heaviest
+// first) share the workspace slots; ring_rows = the largest ring of any grid
+hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, hipStream_t st);
+// wavefronts of the PCG kernel at block S that fit the device at once
+int pcg_max_waves(int S, int ring_rows);
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st);
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
                                 const double *theta_b, const double *rhs, double *rho, hipStream_t st);
-hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta, hipStream_t st);
+// theta_b[k] += x[k] for the buses k >= 1
+hipError_t launch_base_accumulate(int n_bus, double *theta_b, const double *x, hipStream_t st);
 // q = A_c p over ncols / S tiles of n_r x S (bw: bandwidth of A).  Rows are
 // cut into chunks of ch (a multiple of 256 / S that spmm_chunk_fits accepts)
 // and chunks into segments of nseg, one work-group per (tile, segment);

@@ -34,13 +34,13 @@ __device__ __forceinline__ void dd_fma(double &hi, double &lo, double a, double 
 }
 
 // ---------------------------------------------------------------------------
-// Outputs: theta = theta_b + delta on the main system, 0 on islands and at
-// the slack; island flags.
-__global__ void theta_out_kernel(OutParams p) {
+// Island flags of each scenario (the angles themselves are written by the
+// PCG kernel when a scenario stops).
+__global__ void island_out_kernel(OutParams p) {
     const int s = blockIdx.x;
     const int k = blockIdx.y * blockDim.x + threadIdx.x;
     if (k >= p.n_bus) return;
-    int c = p.outages[s];
+    const int c = p.outages[s];
     const bool bad = c < -1 || c >= p.m;
     int lo = 0, hi = 0;
     if (!bad && c >= 0) {
@@ -48,16 +48,7 @@ __global__ void theta_out_kernel(OutParams p) {
         hi = p.isl_hi[c];
     }
     const bool in = (k > 0) && in_interval(p.pre_bus[k], lo, hi);
-    double th = 0.0;
-    if (k > 0 && !in && !bad) {
-        const int j = p.pos ? p.pos[s] : s;
-        const int tile = j / p.S, sc = j % p.S;
-        // delta is the first of the pair {delta, p} of (row k - 1, column sc)
-        th = (p.add_base ? p.theta_b[k] : 0.0) +
-             p.ws[(size_t)tile * kVectors * vec_stride(p.n_r, p.S) + ((size_t)(k - 1) * p.S + sc) * 2];
-    }
-    p.x_out[(size_t)s * p.n_bus + k] = th;
-    if (p.island_out) p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
+    p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
 }
 
 // Branch flows (theta_f - theta_t) / x_e; the outaged branch carries 0 and
@@ -142,11 +133,10 @@ __global__ void base_residual_kernel(int n_r, const int32_t *__restrict__ rowptr
     rho[i] = h + l;
 }
 
-// theta_b += delta, delta read from the {delta, p} pairs of tile 0 of a
-// one-column (S = 1) workspace
-__global__ void base_accumulate_kernel(int n_r, double *theta_b, const double *delta_p) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_r) theta_b[i + 1] += delta_p[2 * i];
+// theta_b += x over the buses other than the slack
+__global__ void base_accumulate_kernel(int n_bus, double *theta_b, const double *x) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 1 && k < n_bus) theta_b[k] += x[k];
 }
 
 __global__ void __launch_bounds__(256) sumsq_kernel(int n, const double *v, double *out) {
@@ -726,7 +716,8 @@ hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st) {
     if (prm.n_out <= 0) return hipSuccess;
     const int tb = 256;
-    hipLaunchKernelGGL(theta_out_kernel, dim3(prm.n_out, (prm.n_bus + tb - 1) / tb), dim3(tb), 0, st, prm);
+    if (prm.island_out)
+        hipLaunchKernelGGL(island_out_kernel, dim3(prm.n_out, (prm.n_bus + tb - 1) / tb), dim3(tb), 0, st, prm);
     if (prm.flows_out)
         hipLaunchKernelGGL(flows_out_kernel, dim3(prm.n_out, (prm.m + tb - 1) / tb), dim3(tb), 0, st, prm);
     if (prm.resid_out) hipLaunchKernelGGL(resid_kernel, dim3(prm.n_out), dim3(256), 0, st, prm);
@@ -741,9 +732,9 @@ hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *c
     return hipGetLastError();
 }
 
-hipError_t launch_base_accumulate(int n_r, double *theta_b, const double *delta, hipStream_t st) {
-    if (n_r <= 0) return hipSuccess;
-    hipLaunchKernelGGL(base_accumulate_kernel, dim3((n_r + 255) / 256), dim3(256), 0, st, n_r, theta_b, delta);
+hipError_t launch_base_accumulate(int n_bus, double *theta_b, const double *x, hipStream_t st) {
+    if (n_bus <= 1) return hipSuccess;
+    hipLaunchKernelGGL(base_accumulate_kernel, dim3((n_bus + 255) / 256), dim3(256), 0, st, n_bus, theta_b, x);
     return hipGetLastError();
 }
 

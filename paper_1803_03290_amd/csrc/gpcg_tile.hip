@@ -485,199 +485,307 @@ __device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, doub
 }
 
 // ---------------------------------------------------------------------------
-// The tile kernel: init, then PCG iterations until every column stops.
-template <int S, int D, int DP>
-__device__ __forceinline__ void pcg_tile(const PcgParams &p, const int tile, double *ring) {
+// Persistent waves.  Every wavefront of the launch owns one workspace slot
+// (the four vectors of S columns) and pulls scenarios from an atomic queue:
+// whenever a column has stopped (and its last step length has reached
+// delta), the column writes its results and takes the next scenario, so no
+// lane sweeps a finished column while scenarios are left.  The iteration
+// itself is per column: its own step count, alpha, rho and stop decision;
+// the sweeps are shared by the S columns, so every matrix and factor entry a
+// wave reads still serves S scenarios.
+
+// One column's scenario (the same in the R lanes of the column).
+struct Col {
+    int scen = -1;  // scenario index; -1: the column holds none
+    int ic = -1, jc = -1, lo = 0, hi = 0;  // outaged branch's reduced rows, island interval
+    double bc = 0.0;                       // its susceptance
+    double bb = 0.0;                       // ||b_M||^2
+    double gfac = 0.0;                     // re-dispatch factor dP / S_gen
+    bool island = false, nogen = false, bad = false;
+    int status = kConverged;
+    int k = 0;  // step-length updates applied so far
+};
+
+// Take scenario `scen` into this lane's column when `take` (column-uniform):
+// island interval, re-dispatch (Section IV.C) and the correction-form start
+// r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
+// from the base state, or r0 = b_M for per-scenario right-hand sides and for
+// the zero start; delta = p = q = 0.  Every lane runs the loops and the
+// column sums (the butterflies need the whole wave); only taking columns
+// touch memory.  Returns the column's squared residual norm.
+template <int S>
+__device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T, int rs, int sc, bool take, int scen,
+                                              Col &col) {
     constexpr int R = kWave / S;
-    const int lane = threadIdx.x;
-    const int sc = lane % S;
-    const int rs = lane / S;
-    const int posn = tile * S + sc;  // tile position of this column
-    const bool valid = posn < p.n_out;
-    const int scen = valid ? (p.order ? p.order[posn] : posn) : posn;
     const int nr = p.n_r;
-    Tile T;
-    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + ((size_t)tile * kVectors + v) * vec_stride(nr, S);
-    T.xp = T.v[0];
-    T.ry = T.v[2];
-    T.nr = nr;
-
-    // ---- per-column outage data -------------------------------------------
-    int c = valid ? p.outages[scen] : -1;
-    const bool bad = valid && (c < -1 || c >= p.m);
-    if (bad) c = -1;
-    int ic = -1, jc = -1, lo = 0, hi = 0;
-    double bc = 0.0;
-    if (c >= 0) {
-        ic = p.br_from[c] - 1;
-        jc = p.br_to[c] - 1;
-        bc = p.br_b[c];
-        lo = p.isl_lo[c];
-        hi = p.isl_hi[c];
+    Col c{};
+    int oc = -1;
+    if (take) {
+        c.scen = scen;
+        oc = p.outages[scen];
+        c.bad = oc < -1 || oc >= p.m;
+        if (c.bad) oc = -1;
+        if (oc >= 0) {
+            c.ic = p.br_from[oc] - 1;
+            c.jc = p.br_to[oc] - 1;
+            c.bc = p.br_b[oc];
+            c.lo = p.isl_lo[oc];
+            c.hi = p.isl_hi[oc];
+        }
+        if (c.bad) {
+            c.lo = 0;
+            c.hi = INT_MAX;
+        }
+        c.island = c.hi > c.lo;
     }
-    if (bad) {
-        lo = 0;
-        hi = INT_MAX;
-    }
-    const bool island = hi > lo;
-
     const bool cols = p.rhs_cols != nullptr;
-    double rr = 0.0, bb = 0.0, gfac = 0.0;
-    bool nogen = false;
+    double rr = 0.0, bb = 0.0;
     if (cols) {
-        // ---- per-scenario right-hand side, zero start: r0 = b restricted to M
-        const double *b = p.rhs_cols + (size_t)(valid ? scen : 0) * p.rhs_ld + 1;
+        const double *b = p.rhs_cols + (size_t)(take ? scen : 0) * p.rhs_ld + 1;
         for (int i = rs; i < nr; i += R) {
-            const double r0 = (valid && !in_interval(p.pre_row[i], lo, hi)) ? b[i] : 0.0;
-            rr += r0 * r0;
-            const unsigned o = row_off<S>(T, i, sc);
-            xp_put(T, o, 0.0, 0.0);
-            ry_put(T, o, r0, 0.0);  // q = 0
+            if (take) {
+                const double r0 = !in_interval(p.pre_row[i], c.lo, c.hi) ? b[i] : 0.0;
+                rr += r0 * r0;
+                const unsigned o = row_off<S>(T, i, sc);
+                xp_put(T, o, 0.0, 0.0);
+                ry_put(T, o, r0, 0.0);  // q = 0
+            }
         }
         bb = rr;
     } else {
-        // ---- re-dispatch (Section IV.C): islanded power over main generators
         double dP = 0.0, Sg = 0.0;
         for (int i = rs; i < nr; i += R) {
-            const double Pk = p.rhs[i + 1];
-            if (in_interval(p.pre_row[i], lo, hi))
-                dP += Pk;
-            else if (Pk > 0.0)
-                Sg += Pk;
+            if (take) {
+                const double Pk = p.rhs[i + 1];
+                if (in_interval(p.pre_row[i], c.lo, c.hi))
+                    dP += Pk;
+                else if (Pk > 0.0)
+                    Sg += Pk;
+            }
         }
         dP = col_sum<S>(dP);
         Sg = col_sum<S>(Sg);
-        nogen = island && !(Sg > 0.0);
-        gfac = (p.kind == 0 && island && !bad && !nogen) ? dP / Sg : 0.0;
-
-        // ---- correction-form start from the base state ----------------------
-        // r0 = (P' - P)_M + (P - A theta_b)_M + b_c (theta_b,f - theta_b,t) u_M
-        const double thf = (ic >= 0) ? p.theta_b[ic + 1] : 0.0;
-        const double tht = (jc >= 0) ? p.theta_b[jc + 1] : 0.0;
-        const double corr = bc * (thf - tht);
+        c.nogen = c.island && !(Sg > 0.0);
+        c.gfac = (p.kind == 0 && c.island && !c.bad && !c.nogen) ? dP / Sg : 0.0;
+        const double thf = (c.ic >= 0) ? p.theta_b[c.ic + 1] : 0.0;
+        const double tht = (c.jc >= 0) ? p.theta_b[c.jc + 1] : 0.0;
+        const double corr = c.bc * (thf - tht);
         for (int i = rs; i < nr; i += R) {
-            double r0 = 0.0;
-            if (!in_interval(p.pre_row[i], lo, hi)) {
-                const double Pk = p.rhs[i + 1];
-                const double dPk = (gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0;
-                const double b = Pk + dPk;
-                if (p.zero_start) {
-                    r0 = b;
-                } else {
-                    r0 = dPk + p.rho_b[i];
-                    if (i == ic) r0 += corr;
-                    if (i == jc) r0 -= corr;
+            if (take) {
+                double r0 = 0.0;
+                if (!in_interval(p.pre_row[i], c.lo, c.hi)) {
+                    const double Pk = p.rhs[i + 1];
+                    const double dPk = (c.gfac != 0.0 && Pk > 0.0) ? Pk * c.gfac : 0.0;
+                    const double b = Pk + dPk;
+                    if (p.zero_start) {
+                        r0 = b;
+                    } else {
+                        r0 = dPk + p.rho_b[i];
+                        if (i == c.ic) r0 += corr;
+                        if (i == c.jc) r0 -= corr;
+                    }
+                    bb += b * b;
                 }
-                bb += b * b;
+                rr += r0 * r0;
+                const unsigned o = row_off<S>(T, i, sc);
+                xp_put(T, o, 0.0, 0.0);
+                ry_put(T, o, r0, 0.0);  // q = 0
             }
-            rr += r0 * r0;
-            const unsigned o = row_off<S>(T, i, sc);
-            xp_put(T, o, 0.0, 0.0);
-            ry_put(T, o, r0, 0.0);  // q = 0
         }
-    }
-    if (rs == 0) {
-        const unsigned o = row_off<S>(T, nr, sc);
-        xp_put(T, o, 0.0, 0.0);
-        ry_put(T, o, 0.0, 0.0);
     }
     rr = col_sum<S>(rr);
     bb = col_sum<S>(bb);
-
-    int status = kConverged;
-    int iters = 0;
-    bool done;
-    if (!valid) {
-        done = true;
-    } else if (bad) {
-        done = true;
-        status = kBadOutage;
-    } else if (!__builtin_isfinite(rr) || !__builtin_isfinite(bb)) {
-        done = true;
-        status = kNonfinite;
-    } else {
-        done = rr <= p.tol2 * bb;
+    if (take) {
+        c.bb = bb;
+        c.status = c.bad ? kBadOutage
+                         : ((!__builtin_isfinite(rr) || !__builtin_isfinite(bb)) ? kNonfinite : kConverged);
+        col = c;
     }
-    __syncthreads();
+    return rr;
+}
 
+// Write a stopped column's results: x = theta_b + delta (or delta alone for
+// per-scenario right-hand sides and the zero start) on the main system, 0 on
+// islanded buses and at the slack; its step count, status and re-dispatch
+// factor.  Only retiring columns touch memory.
+template <int S>
+__device__ __forceinline__ void column_retire(const PcgParams &p, const Tile &T, int rs, int sc, bool retire,
+                                              const Col &c) {
+    constexpr int R = kWave / S;
+    if (!retire) return;
+    double *x = p.x_out + (size_t)c.scen * p.n_bus;
+    for (int i = rs; i < p.n_r; i += R) {
+        double v = 0.0;
+        if (!in_interval(p.pre_row[i], c.lo, c.hi))
+            v = (p.add_base ? p.theta_b[i + 1] : 0.0) + xp_get(T, row_off<S>(T, i, sc)).x;
+        x[i + 1] = v;
+    }
+    if (rs == 0) {
+        x[0] = 0.0;
+        int st = c.status;
+        if (st == kConverged && c.island) st = (p.kind == 0 && c.nogen) ? kIslandedNoGen : kConvergedIslanded;
+        p.iters_out[c.scen] = c.k;
+        p.status_out[c.scen] = st;
+        p.gfac_out[c.scen] = c.gfac;
+    }
+}
+
+// Retire every stopped column and refill the free ones from the queue, until
+// every column is busy or the queue is empty.  A column whose new scenario
+// stops at once (a bad id, a start that already meets the stop test) is
+// retired and refilled in the next round.
+template <int S>
+__device__ __forceinline__ void refill(const PcgParams &p, const Tile &T, int rs, int sc, Col &col, bool &done,
+                                       double &alpha, double &rho, bool &drained) {
+    const int lane = threadIdx.x;
+    for (;;) {
+        const bool retire = col.scen >= 0 && done;
+        if (__any(retire)) column_retire<S>(p, T, rs, sc, retire, col);
+        if (retire) col.scen = -1;
+        if (drained) return;
+        const bool want = col.scen < 0;
+        const unsigned long long wmask = __ballot(want && rs == 0);  // lanes 0 .. S-1 carry rs == 0
+        if (wmask == 0ull) return;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(p.queue, __popcll(wmask));
+        base = __shfl(base, 0);
+        const int j = base + __popcll(wmask & ((1ull << sc) - 1ull));
+        const bool take = want && j < p.n_out;
+        if (base + __popcll(wmask) >= p.n_out) drained = true;
+        if (!__any(take)) return;
+        const int scen = take ? (p.order ? p.order[p.n_out - 1 - j] : j) : 0;
+        const double rr = column_init<S>(p, T, rs, sc, take, scen, col);
+        if (take) {
+            done = col.status != kConverged || rr <= p.tol2 * col.bb;
+            alpha = 0.0;
+            rho = 0.0;
+        }
+        if (!__any(take && done)) return;
+    }
+}
+
+// The PCG of every scenario this wave takes (Section III.A), in correction
+// form from the base state (Section III.B), with the base-case ILU(0)
+// preconditioner (Section IV.B).  Per iteration: forward sweep (r -= alpha q,
+// ||r||^2, y = L^-1 r), stop test, backward sweep (z = P_M U^-1 y, r'z),
+// beta, product sweep (delta += alpha p_old, p = z + beta p, q = A_c p with
+// the outaged branch shielded, p'q), alpha.  Returns the iterations the wave
+// ran (sweeps of its columns, counting stopped ones).
+template <int S, int D, int DP>
+__device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, double *ring) {
+    const int lane = threadIdx.x;
+    const int sc = lane % S;
+    const int rs = lane / S;
+    Tile T;
+    for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + (size_t)wave * p.ws_slot + (size_t)v * vec_stride(p.n_r, S);
+    T.xp = T.v[0];
+    T.ry = T.v[2];
+    T.nr = p.n_r;
+    if (rs == 0) {  // the scratch row holds zeros for idle slots
+        const unsigned o = row_off<S>(T, p.n_r, sc);
+        xp_put(T, o, 0.0, 0.0);
+        ry_put(T, o, 0.0, 0.0);
+    }
+    Col col;
+    bool done = true, drained = false;
     double alpha = 0.0, rho = 0.0;
-    for (int k = 0;; ++k) {
-        // ---- forward sweep: delta += alpha p, r -= alpha q, y = L^-1 r ----
+    refill<S>(p, T, rs, sc, col, done, alpha, rho, drained);
+    long long sweeps = 0;
+    while (__any(col.scen >= 0)) {
+        __syncthreads();
+        ++sweeps;
+        // ---- forward sweep: r -= alpha q, y = L^-1 r ----------------------
         double rrp = fwd_sweep<S, D>(p.fwd, ring, T, rs, sc, alpha);
         __syncthreads();
         rrp = col_sum<S>(rrp);
-        if (k > 0 && !done) {
-            iters = k;
-            if (!__builtin_isfinite(rrp)) {
-                done = true;
-                status = kNonfinite;
-            } else if (rrp <= p.tol2 * bb) {
+        if (col.scen >= 0 && !done) {
+            if (col.k > 0) {
+                if (!__builtin_isfinite(rrp)) {
+                    done = true;
+                    col.status = kNonfinite;
+                } else if (rrp <= p.tol2 * col.bb) {
+                    done = true;
+                }
+            }
+            if (!done && col.k >= p.max_iter) {
+                col.status = kMaxIter;
                 done = true;
             }
         }
-        if (k >= p.max_iter && !done) {
-            status = kMaxIter;
-            done = true;
-        }
         if (__all(done)) {
-            // the last step length has not reached delta yet
+            // every column stopped: the last step length has not reached
+            // delta yet; then hand the columns back
             final_update<S>(T, rs, sc, alpha);
-            break;
+            alpha = 0.0;
+            refill<S>(p, T, rs, sc, col, done, alpha, rho, drained);
+            continue;
         }
 
         // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
-        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, lo, hi));
+        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, col.lo, col.hi));
         __syncthreads();
-        const double beta = (k == 0 || done) ? 0.0 : rz / rho;
+        const double beta = (col.k == 0 || done) ? 0.0 : rz / rho;
         rho = rz;
 
         // ---- p = z + beta p and q = A_c p (outaged branch shielded), p'q ---
-        const double sigma =
-            col_sum<S>(prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc));
+        const double sigma = col_sum<S>(
+            prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, col.lo, col.hi, col.ic, col.jc, col.bc));
         __syncthreads();
         if (!done) {
             if (!__builtin_isfinite(sigma) || !__builtin_isfinite(rho)) {
                 done = true;
-                status = kNonfinite;
+                col.status = kNonfinite;
             } else if (!(sigma > 0.0)) {
                 done = true;
-                status = kBreakdown;
+                col.status = kBreakdown;
             } else {
                 alpha = rho / sigma;
+                ++col.k;
             }
         }
-        if (done) alpha = 0.0;
+        if (done) alpha = 0.0;  // a stopped column's delta is complete after this product sweep
+        if (__any(col.scen >= 0 && done)) refill<S>(p, T, rs, sc, col, done, alpha, rho, drained);
     }
-
-    if (valid && rs == 0) {
-        int st = status;
-        if (st == kConverged && island) st = (p.kind == 0 && nogen) ? kIslandedNoGen : kConvergedIslanded;
-        p.iters_out[scen] = iters;
-        p.status_out[scen] = st;
-        p.gfac_out[scen] = gfac;
-    }
+    return sweeps;
 }
 
-// One grid: work-group b solves tile tile0 + b.
+// Work-group b (one wavefront) is persistent wave b.
 template <int S, int D, int DP>
-__global__ void __launch_bounds__(kWave) pcg_tile_kernel(PcgParams p) {
+__global__ void __launch_bounds__(kWave) pcg_wave_kernel(PcgParams p) {
     extern __shared__ double ring[];
-    pcg_tile<S, D, DP>(p, blockIdx.x + p.tile0, ring);
+    const long long n = pcg_wave<S, D, DP>(p, blockIdx.x, ring);
+    if (p.sweeps && threadIdx.x == 0) atomicAdd(p.sweeps, (unsigned long long)n);
 }
 
-// Several grids in one launch (the uneven batch): work-group b solves tile
-// tile0 + b - tile_start[g] of grid g, tile_start ascending with
-// tile_start[0] = 0.  Grids are ordered by the caller, heaviest first, so
-// the dispatcher hands out the longest tiles before the short ones.
+// Several grids (the uneven batch): every wave works through the grids in
+// the caller's order (heaviest first), each until that grid's queue is
+// empty and its own columns have stopped, so waves done with a large grid
+// move on to the smaller ones while the others finish.
 template <int S, int D, int DP>
-__global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, const int *tile_start,
-                                                          int n_grids) {
+__global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, int n_grids) {
     extern __shared__ double ring[];
-    const int b = blockIdx.x;
-    int g = 0;
-    while (g + 1 < n_grids && tile_start[g + 1] <= b) ++g;
-    const PcgParams &p = grids[g];
-    pcg_tile<S, D, DP>(p, p.tile0 + b - tile_start[g], ring);
+    long long n = 0;
+    for (int g = 0; g < n_grids; ++g) {
+        const PcgParams &p = grids[g];
+        n += pcg_wave<S, D, DP>(p, blockIdx.x, ring);
+        __syncthreads();
+    }
+    if (grids[0].sweeps && threadIdx.x == 0) atomicAdd(grids[0].sweeps, (unsigned long long)n);
+}
+
+// Queue counters (and the sweep counter) back to zero before a launch; a
+// kernel rather than a memory set, so that graph replays see it too.
+__global__ void queue_reset_kernel(const PcgParams *grids, int n_grids, int32_t *queue, unsigned long long *sweeps) {
+    const int t = threadIdx.x;
+    if (grids) {
+        for (int g = t; g < n_grids; g += blockDim.x) {
+            *grids[g].queue = 0;
+            if (grids[g].sweeps) *grids[g].sweeps = 0ull;
+        }
+    } else if (t == 0) {
+        *queue = 0;
+        if (sweeps) *sweeps = 0ull;
+    }
 }
 
 }  // namespace
@@ -687,56 +795,89 @@ constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
 constexpr int kPrefetchProd = 6;  // steps of prefetch in the product sweep
 
 template <int S>
-static hipError_t launch_pcg_s(const PcgParams &prm, int n_tiles, size_t lds, hipStream_t st) {
-    auto kern = pcg_tile_kernel<S, kPrefetch, kPrefetchProd>;
+static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, hipStream_t st) {
+    auto kern = pcg_wave_kernel<S, kPrefetch, kPrefetchProd>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, prm);
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(kWave), 0, st, (const PcgParams *)nullptr, 0, prm.queue,
+                       prm.sweeps);
+    hipLaunchKernelGGL(kern, dim3(n_waves), dim3(kWave), lds, st, prm);
     return hipGetLastError();
 }
 
 template <int S>
-static hipError_t launch_multi_s(const PcgParams *grids, const int *tile_start, int n_grids, int n_tiles, size_t lds,
-                                 hipStream_t st) {
+static hipError_t launch_multi_s(const PcgParams *grids, int n_grids, int n_waves, size_t lds, hipStream_t st) {
     auto kern = pcg_multi_kernel<S, kPrefetch, kPrefetchProd>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(kWave), lds, st, grids, tile_start, n_grids);
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(kWave), 0, st, grids, n_grids, (int32_t *)nullptr,
+                       (unsigned long long *)nullptr);
+    hipLaunchKernelGGL(kern, dim3(n_waves), dim3(kWave), lds, st, grids, n_grids);
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_multi(const PcgParams *grids, const int *tile_start, int n_grids, int S, int n_tiles,
-                            int ring_rows, hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
-    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
+template <int S>
+static int max_waves_s(size_t lds) {
+    int per_cu = 0, cu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    auto kern = pcg_wave_kernel<S, kPrefetch, kPrefetchProd>;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kWave, lds) != hipSuccess) return 0;
+    return per_cu * cu;
+}
+
+static size_t ring_lds(int ring_rows, int S) {
+    // ring rows plus the zero row and the trash row of idle slots
+    return (size_t)(ring_rows + 2) * S * sizeof(double);
+}
+
+int pcg_max_waves(int S, int ring_rows) {
+    const size_t lds = ring_lds(ring_rows, S);
     switch (S) {
-        case 1: return launch_multi_s<1>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 2: return launch_multi_s<2>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 4: return launch_multi_s<4>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 8: return launch_multi_s<8>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 16: return launch_multi_s<16>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 32: return launch_multi_s<32>(grids, tile_start, n_grids, n_tiles, lds, st);
-        case 64: return launch_multi_s<64>(grids, tile_start, n_grids, n_tiles, lds, st);
+        case 1: return max_waves_s<1>(lds);
+        case 2: return max_waves_s<2>(lds);
+        case 4: return max_waves_s<4>(lds);
+        case 8: return max_waves_s<8>(lds);
+        case 16: return max_waves_s<16>(lds);
+        case 32: return max_waves_s<32>(lds);
+        case 64: return max_waves_s<64>(lds);
+        default: return 0;
+    }
+}
+
+hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, hipStream_t st) {
+    if (n_waves <= 0 || n_grids <= 0) return hipSuccess;
+    const size_t lds = ring_lds(ring_rows, S);
+    switch (S) {
+        case 1: return launch_multi_s<1>(grids, n_grids, n_waves, lds, st);
+        case 2: return launch_multi_s<2>(grids, n_grids, n_waves, lds, st);
+        case 4: return launch_multi_s<4>(grids, n_grids, n_waves, lds, st);
+        case 8: return launch_multi_s<8>(grids, n_grids, n_waves, lds, st);
+        case 16: return launch_multi_s<16>(grids, n_grids, n_waves, lds, st);
+        case 32: return launch_multi_s<32>(grids, n_grids, n_waves, lds, st);
+        case 64: return launch_multi_s<64>(grids, n_grids, n_waves, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pcg(const PcgParams &prm, int S, int n_tiles, int ring_rows, hipStream_t st) {
-    if (n_tiles <= 0) return hipSuccess;
-    // ring rows plus the zero row and the trash row of idle slots
-    const size_t lds = (size_t)(ring_rows + 2) * S * sizeof(double);
+hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, hipStream_t st) {
+    if (n_waves <= 0) return hipSuccess;
+    const size_t lds = ring_lds(ring_rows, S);
     switch (S) {
-        case 1: return launch_pcg_s<1>(prm, n_tiles, lds, st);
-        case 2: return launch_pcg_s<2>(prm, n_tiles, lds, st);
-        case 4: return launch_pcg_s<4>(prm, n_tiles, lds, st);
-        case 8: return launch_pcg_s<8>(prm, n_tiles, lds, st);
-        case 16: return launch_pcg_s<16>(prm, n_tiles, lds, st);
-        case 32: return launch_pcg_s<32>(prm, n_tiles, lds, st);
-        case 64: return launch_pcg_s<64>(prm, n_tiles, lds, st);
+        case 1: return launch_wave_s<1>(prm, n_waves, lds, st);
+        case 2: return launch_wave_s<2>(prm, n_waves, lds, st);
+        case 4: return launch_wave_s<4>(prm, n_waves, lds, st);
+        case 8: return launch_wave_s<8>(prm, n_waves, lds, st);
+        case 16: return launch_wave_s<16>(prm, n_waves, lds, st);
+        case 32: return launch_wave_s<32>(prm, n_waves, lds, st);
+        case 64: return launch_wave_s<64>(prm, n_waves, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
