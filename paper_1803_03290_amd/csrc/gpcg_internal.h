@@ -11,7 +11,7 @@
 namespace gpcg {
 
 constexpr int kWave = 64;     // gfx950 wavefront width
-constexpr int kVectors = 4;   // per tile: pairs {delta, p} and pairs {r, w} (w: y, z, then q), (n_r + 1) x S each
+constexpr int kVectors = 4;   // per wave: pairs {delta, p} (two vectors), r, w (y, z, then q); (n_r + 1) x S each
 // doubles per vector of a tile: (n_r + 1) rows x S columns, rounded up to
 // even so that every vector, and every {delta, p} pair, is 16-byte aligned
 constexpr size_t vec_stride(int n_r, int S) { return ((size_t)(n_r + 1) * S + 1) / 2 * 2; }
@@ -97,7 +97,7 @@ struct PcgParams {
     unsigned long long *sweeps;    // NULL, or the sum over waves of the iterations each ran
     double tol2;
     int max_iter;
-    // workspace: wave w owns ws + w * ws_slot: pairs {delta, p}, pairs {r, w},
+    // workspace: wave w owns ws + w * ws_slot: pairs {delta, p}, r, w,
     // kVectors x (n_r + 1) rows x S
     double *ws;
     size_t ws_slot;
