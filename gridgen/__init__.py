@@ -19,10 +19,12 @@ order):
    (length, i, j), until ``m`` branches exist (no parallel branches);
 3. slack: the highest-degree bus of the largest 2-edge-connected component
    (ties go to the bus nearest the centre), relabelled to index 0; the other
-   buses are numbered 1..n-1 in reverse Cuthill-McKee order of the graph with
-   the slack removed (``order="rcm"``, the default) or keep their generation
-   order (``order="generated"``).  The numbering is part of the input: every
-   consumer stores the reduced rows in bus order;
+   buses keep their generation order as 1..n-1 (``order="generated"``, the
+   default: the numbering of the points, unrelated to the graph), or are
+   numbered in reverse Cuthill-McKee order of the graph with the slack
+   removed (``order="rcm"``).  A banded row order is a solver's concern:
+   ``rcm_perm`` gives the reverse Cuthill-McKee row order of a grid for a
+   consumer that wants one, and ``renumber`` relabels a grid by it;
 4. branches sorted by (min endpoint, max endpoint); ``from`` is the smaller;
 5. reactances ``x ~ U(x_lo, 0.3)``; optionally a seeded 5 % of branches become
    transformers with ``x ~ U(0.05, 0.2)``;
@@ -42,7 +44,7 @@ import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components, minimum_spanning_tree
 from scipy.spatial import Delaunay, cKDTree
 
-__all__ = ["Grid", "GridSpec", "SPECS", "make_grid", "hand_grid", "HAND_GRIDS"]
+__all__ = ["Grid", "GridSpec", "SPECS", "make_grid", "hand_grid", "HAND_GRIDS", "rcm_perm", "renumber"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -57,7 +59,7 @@ class GridSpec:
     x_hi: float = 0.3
     transformer_share: float = 0.0
     reactive: bool = False
-    order: str = "rcm"
+    order: str = "generated"
 
 
 # The five workloads: a 200-bus grid, a 2,000-bus grid, a 10,000-bus grid
@@ -141,10 +143,13 @@ def _two_edge_components(n: int, edges: np.ndarray) -> np.ndarray:
     return lab
 
 
-def make_grid(spec: GridSpec | str) -> Grid:
-    """Draw the grid described by ``spec`` (a GridSpec or a key of SPECS)."""
+def make_grid(spec: GridSpec | str, order: Optional[str] = None) -> Grid:
+    """Draw the grid described by ``spec`` (a GridSpec or a key of SPECS),
+    optionally with another bus numbering ("generated" or "rcm")."""
     if isinstance(spec, str):
         spec = SPECS[spec]
+    if order is not None:
+        spec = dataclasses.replace(spec, order=order)
     n, m = spec.n, spec.m
     if m < n - 1:
         raise ValueError("a connected grid needs m >= n - 1")
@@ -267,3 +272,30 @@ def _rcm_order(n: int, edges: np.ndarray, slack: int, rest: np.ndarray) -> np.nd
     G = sp.coo_matrix((np.ones(len(f)), (f, t)), shape=(k, k)).tocsr()
     G = (G + G.T).tocsr()
     return np.asarray(reverse_cuthill_mckee(G, symmetric_mode=True), dtype=np.int64)
+
+
+def rcm_perm(grid: Grid) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the non-slack buses (SciPy's), as the
+    bus of each reduced row: perm[k] is the bus held in row k."""
+    n = grid.n
+    edges = np.stack([grid.br_from, grid.br_to], axis=1).astype(np.int64)
+    rest = np.arange(1, n, dtype=np.int64)
+    return rest[_rcm_order(n, edges, 0, rest)].astype(np.int32)
+
+
+def renumber(grid: Grid, perm: np.ndarray) -> Grid:
+    """The same grid with bus perm[k] relabelled k + 1 (the slack stays 0);
+    branches keep their order and orientation, so outage ids and flows are
+    unchanged."""
+    n = grid.n
+    new = np.zeros(n, np.int64)
+    new[np.asarray(perm, np.int64)] = np.arange(1, n)
+    old = np.zeros(n, np.int64)
+    old[new] = np.arange(n)
+
+    def bus(a):
+        return None if a is None else np.asarray(a)[old]
+
+    return Grid(grid.name + ":renumbered", n, new[grid.br_from].astype(np.int32), new[grid.br_to].astype(np.int32),
+                grid.x.copy(), bus(grid.P), bus(grid.Q), bus(grid.bsh),
+                None if grid.pts is None else grid.pts[old], grid.seed)

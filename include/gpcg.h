@@ -16,10 +16,15 @@
  * (Section IV.C).
  *
  * Conventions shared by every entry point.
- *  - Bus 0 is the slack.  The reduced system drops it: reduced row k is
- *    bus k + 1, so n_r = n_bus - 1.  Buses are used in the caller's
- *    numbering; a banded numbering (e.g. reverse Cuthill-McKee) makes the
- *    ILU(0) preconditioner much stronger.
+ *  - Bus 0 is the slack.  The reduced system drops it, so n_r = n_bus - 1.
+ *    Its rows are the non-slack buses in a row order: bus k + 1 in row k,
+ *    or the order of a permutation (gpcg_options.perm, or the library's own
+ *    reverse Cuthill-McKee order with gpcg_options.reorder).  A banded row
+ *    order makes the ILU(0) preconditioner much stronger and is what the
+ *    kernels' LDS windows need.  Matrices (A, L, U) are in row order; every
+ *    array indexed by bus (injections, angles, island flags, ...) is in the
+ *    caller's bus numbering whatever the row order; arrays indexed by
+ *    branch follow the caller's branch table.
  *  - Matrices are CSR with int32 indices, column indices sorted within
  *    each row, FP64 values.
  *  - "host" pointers are ordinary CPU memory and are only read during the
@@ -85,6 +90,11 @@ typedef struct {
     int32_t lookahead;     /* rows the triangular-solve scheduler may look ahead; 0 = 256 */
     int32_t zero_start;    /* 1: every scenario starts from x0 = 0 (the listing of Section III.A)
                               instead of the base state (Section III.B); 0 = base state */
+    int32_t reorder;       /* 1: A is given in bus order (row k = bus k + 1) and L, U are NULL;
+                              gpcg_setup orders the rows by gpcg_rcm, permutes A and forms the
+                              ILU(0) itself (Section IV.B) */
+    const int32_t *perm;   /* host, n_bus - 1 entries, or NULL: perm[k] is the bus held in row k
+                              (each bus 1 .. n_bus - 1 once); A, L, U are then in that row order */
 } gpcg_options;
 
 /* Context facts, for logging and for the roofline accounting. */
@@ -113,13 +123,29 @@ const char *gpcg_last_error(void);
  * column dropped.  Parallel branches add up.
  *   from, to, x: host, m entries; 0 <= from, to < n_bus, from != to, x > 0.
  *   shunt: host, n_bus entries, or NULL.
+ *   perm: host, n_bus - 1 entries, or NULL: rows in that order (row k =
+ *     bus perm[k]), else row k = bus k + 1.
  *   rowptr: host output, n_bus entries (n_r + 1).
  *   col, val: host outputs with room for cap entries; cap >= n_bus - 1 + 2m
  *   always suffices.  *nnz_out receives the entry count.
+ * Every entry is the exact sum of its terms (each branch's 1/x rounded to
+ * FP64, the shunt) rounded once, so the result does not depend on the
+ * order of the branch table.  Errors: GPCG_E_ARG (bad branch, bad perm,
+ * capacity).
  */
 int gpcg_assemble(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, const double *x,
-                  const double *shunt, int32_t *rowptr, int32_t *col, double *val, int32_t cap,
+                  const double *shunt, const int32_t *perm, int32_t *rowptr, int32_t *col, double *val, int32_t cap,
                   int32_t *nnz_out);
+
+/*
+ * Reverse Cuthill-McKee order of the non-slack buses (the graph of the
+ * reduced system: branches at the slack left out), a banded row order for
+ * gpcg_options.perm.  Every connected piece starts at its bus of least
+ * degree, a breadth-first search appends each bus's unvisited neighbours by
+ * increasing degree (ties by bus number), and the sequence is reversed.  perm: host output, n_bus - 1 entries (buses 1 .. n_bus - 1).
+ * All pointers are host memory.  Errors: GPCG_E_ARG (bad branch).
+ */
+int gpcg_rcm(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, int32_t *perm);
 
 /*
  * Zero-fill incomplete LU of A (Saad, Iterative Methods for Sparse Linear
@@ -155,21 +181,27 @@ int gpcg_topology(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *
 /*
  * Create a context on the current HIP device: upload the reduced matrix A
  * (B' or B'') and its factors L (strictly lower, unit diagonal implied) and
- * U (upper with diagonal) - normally gpcg_ilu0(A), but any factors with the
- * same shapes are accepted, e.g. an exact LU - plus the branch table, run
- * the topology pass and the triangular-solve scheduling, and fix the base
- * state theta_b used as the start of every scenario (Section III.B):
+ * U (upper with diagonal) - normally the ILU(0) of A, but any factors with
+ * the same shapes are accepted, e.g. an exact LU - plus the branch table,
+ * run the topology pass and the triangular-solve scheduling, and fix the
+ * base state theta_b used as the start of every scenario (Section III.B):
  *   - theta_base != NULL: host, n_bus entries (slack entry ignored);
  *   - otherwise theta_b solves A theta = base_rhs on the device by PCG with
  *     iterative refinement whose residual is formed in double-double.
+ * Row order (see the conventions above): A, L, U in bus order (opt NULL or
+ * perm NULL), in opt->perm's order, or, with opt->reorder, A in bus order
+ * and L = U = NULL: the library orders the rows by gpcg_rcm.  L and U may
+ * be NULL without reorder too: the library then forms the ILU(0) of A in
+ * the given row order.  Every bus-indexed input and output of the context
+ * stays in the caller's numbering.
  * base_rhs: host, n_bus entries (slack entry ignored); required when
  * theta_base is NULL, ignored otherwise.
  * stream: a hipStream_t (NULL = the null stream) on which every later
  * operation of the context is enqueued.
- * Errors: GPCG_E_ARG (fewer than two buses, a branch out of range),
- * GPCG_E_UNSUPPORTED (2^20 - 1 buses or more, or a matrix or factor
- * bandwidth whose LDS window exceeds what one wavefront may hold at this
- * block; number the buses in a banded order).
+ * Errors: GPCG_E_ARG (fewer than two buses, a branch out of range, a bad
+ * perm, perm with reorder, only one of L and U), GPCG_E_UNSUPPORTED (2^20 - 1
+ * buses or more, or a row order whose bandwidth needs a larger LDS window
+ * than one wavefront may hold at this block: pass perm or reorder).
  * On error *out is NULL and nothing is leaked.
  */
 int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, const int32_t *br_to,
@@ -183,9 +215,17 @@ void gpcg_destroy(gpcg_t h);
 int gpcg_get_info(gpcg_t h, gpcg_info *info);
 
 /* Copy the topology pass results into host arrays of m entries (is_bridge)
- * and n_bus entries (theta_base: the base state, slack entry 0). Either
- * pointer may be NULL. Synchronises the context's stream. */
+ * and n_bus entries (theta_base: the base state by the caller's bus, slack
+ * entry 0). Either pointer may be NULL. */
 int gpcg_get_base(gpcg_t h, uint8_t *is_bridge, double *theta_base);
+
+/* The bridge flags of the integer topology pass (Section IV.C: removing a
+ * bridge islands part of the grid): is_bridge, host, m entries. */
+int gpcg_bridge_flags(gpcg_t h, uint8_t *is_bridge);
+
+/* The context's row order: perm[k] = the caller's bus held in reduced row
+ * k; host, n_bus - 1 entries.  (A stand-alone gpcg_spmm works in rows.) */
+int gpcg_get_perm(gpcg_t h, int32_t *perm);
 
 /*
  * Solve n_out outage scenarios (the hot path).  Scenario s takes branch
@@ -416,7 +456,7 @@ int gpcg_solve_plain(gpcg_t h, int32_t n_out, const int32_t *outages, const doub
  * ncols scenario columns, with the outaged branch's coupling removed per
  * column (the edge "shielding" of the GPCG listing in Section III.B) and
  * islanded rows zeroed, plus pq[j] = p_j' q_j.  p and q are device f64
- * blocks in the tile-interleaved layout the solver uses:
+ * blocks in the context's row order (gpcg_get_perm) and tile-interleaved:
  * element (row i, column j) sits at ((j / S) * n_r + i) * S + j % S with
  * S = the context's block; ncols must be a multiple of S.
  * outages: device int32[ncols].  pq: device f64[ncols] or NULL.

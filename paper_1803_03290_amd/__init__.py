@@ -22,6 +22,7 @@ from .binding import (  # noqa: F401
     assemble,
     ilu0,
     lib,
+    rcm,
     topology,
 )
 from .overload import OverloadLoss, overload_loss  # noqa: F401,E402

@@ -30,7 +30,7 @@ class _Csr(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("kind", C.c_int32), ("block", C.c_int32), ("base_max_iter", C.c_int32), ("lookahead", C.c_int32),
-                ("zero_start", C.c_int32)]
+                ("zero_start", C.c_int32), ("reorder", C.c_int32), ("perm", _i32p)]
 
 
 class Info(C.Structure):
@@ -50,8 +50,11 @@ class Info(C.Structure):
 _VP = C.c_void_p
 SIGNATURES = {
     "gpcg_last_error": (C.c_char_p, []),
-    "gpcg_assemble": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, _f64p, C.c_int32,
-                                _i32p]),
+    "gpcg_assemble": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, _i32p, _f64p,
+                                C.c_int32, _i32p]),
+    "gpcg_rcm": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _i32p]),
+    "gpcg_bridge_flags": (C.c_int, [_VP, _u8p]),
+    "gpcg_get_perm": (C.c_int, [_VP, _i32p]),
     "gpcg_ilu0": (C.c_int, [C.POINTER(_Csr), _i32p, _i32p, _f64p, _i32p, _i32p, _i32p, _f64p, _i32p]),
     "gpcg_topology": (C.c_int, [C.c_int32, C.c_int32, _i32p, _i32p, _u8p, _i32p, _i32p, _i32p, _i32p]),
     "gpcg_setup": (C.c_int, [C.POINTER(_VP), C.c_int32, C.c_int32, _i32p, _i32p, _f64p, C.POINTER(_Csr),
@@ -144,8 +147,9 @@ class Csr:
         return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
 
 
-def assemble(n_bus, br_from, br_to, x, shunt=None) -> Csr:
-    """gpcg_assemble: reduced B' (or B'' with shunts), slack row/column dropped."""
+def assemble(n_bus, br_from, br_to, x, shunt=None, perm=None) -> Csr:
+    """gpcg_assemble: reduced B' (or B'' with shunts), slack row/column
+    dropped, rows in bus order or in ``perm``'s order."""
     f, t, xx = _i32(br_from), _i32(br_to), _f64(x)
     m = len(f)
     cap = n_bus - 1 + 2 * m
@@ -154,9 +158,19 @@ def assemble(n_bus, br_from, br_to, x, shunt=None) -> Csr:
     val = np.zeros(max(cap, 1), np.float64)
     nnz = C.c_int32(0)
     sh = None if shunt is None else _f64(shunt)
-    _check(lib().gpcg_assemble(n_bus, m, _ip(f), _ip(t), _fp(xx), _fp(sh), _ip(rowptr), _ip(col), _fp(val), cap,
-                               C.byref(nnz)))
+    pm = None if perm is None else _i32(perm)
+    _check(lib().gpcg_assemble(n_bus, m, _ip(f), _ip(t), _fp(xx), _fp(sh), None if pm is None else _ip(pm),
+                               _ip(rowptr), _ip(col), _fp(val), cap, C.byref(nnz)))
     return Csr(rowptr, col[: nnz.value].copy(), val[: nnz.value].copy())
+
+
+def rcm(n_bus, br_from, br_to) -> np.ndarray:
+    """gpcg_rcm: the library's reverse Cuthill-McKee row order (bus of each
+    reduced row)."""
+    f, t = _i32(br_from), _i32(br_to)
+    perm = np.zeros(n_bus - 1, np.int32)
+    _check(lib().gpcg_rcm(n_bus, len(f), _ip(f), _ip(t), _ip(perm)))
+    return perm
 
 
 def ilu0(A: Csr):
@@ -204,15 +218,20 @@ def _ptr(t):
 
 class Context:
     """A device context (gpcg_setup / gpcg_destroy) for one grid and one
-    matrix kind.  ``A``, ``L``, ``U`` default to the library's own assembly
-    and ILU(0) of the branch table; ``precond="jacobi"`` passes L = 0 and
+    matrix kind.  Buses keep the caller's numbering in every input and
+    output.  The row order of the reduced system is ``perm``: "rcm" (the
+    default) lets gpcg_setup order the rows by its reverse Cuthill-McKee
+    pass and form the ILU(0) itself; an array gives the bus of each row
+    (A, L, U, if given, are in that order); None keeps the bus order.
+    ``A`` defaults to the library's own assembly; ``L``, ``U`` to the
+    ILU(0) the library forms; ``precond="jacobi"`` passes L = 0 and
     U = diag(A) instead (the Jacobi preconditioner of the GPCG listing,
     Section III.B).  ``zero_start`` starts every scenario from x0 = 0 (the
     listing of Section III.A) instead of the base state."""
 
     def __init__(self, n_bus, br_from, br_to, x, base_rhs=None, *, shunt=None, kind=KIND_BP, block=64,
                  theta_base=None, A: Csr | None = None, L: Csr | None = None, U: Csr | None = None, lookahead=0,
-                 stream=None, precond="ilu0", zero_start=False):
+                 stream=None, precond="ilu0", zero_start=False, perm="rcm"):
         import torch
 
         if not torch.cuda.is_available():
@@ -220,25 +239,38 @@ class Context:
         self._lib = lib()
         self.n_bus, self.m, self.kind = int(n_bus), len(br_from), kind
         self.br_from, self.br_to, self.x = _i32(br_from), _i32(br_to), _f64(x)
-        self.A = A if A is not None else assemble(n_bus, br_from, br_to, x, shunt)
-        if L is None or U is None:
+        if precond not in ("ilu0", "jacobi"):
+            raise ValueError(f"unknown preconditioner {precond!r}")
+        reorder = False
+        if isinstance(perm, str):
+            if perm != "rcm":
+                raise ValueError(f"unknown row order {perm!r}")
+            if L is not None or U is not None:
+                raise ValueError("factors come with their row order: pass perm as an array or None")
             if precond == "jacobi":
-                L, U = jacobi_factors(self.A)
-            elif precond == "ilu0":
-                L, U = ilu0(self.A)
+                perm = rcm(n_bus, br_from, br_to)
             else:
-                raise ValueError(f"unknown preconditioner {precond!r}")
-        self.L, self.U = L, U
+                perm, reorder = None, True
+        pm = None if perm is None else _i32(perm)
+        self.A = A if A is not None else assemble(n_bus, br_from, br_to, x, shunt, None if reorder else pm)
+        if precond == "jacobi" and (L is None or U is None):
+            L, U = jacobi_factors(self.A)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        opt = _Options(kind, block, 0, lookahead, 1 if zero_start else 0)
-        a, l, u = self.A._c(), L._c(), U._c()
+        opt = _Options(kind, block, 0, lookahead, 1 if zero_start else 0, 1 if reorder else 0,
+                       None if pm is None else _ip(pm))
+        a = self.A._c()
+        l = None if L is None else C.byref(L._c())
+        u = None if U is None else C.byref(U._c())
         h = C.c_void_p()
         rhs = None if base_rhs is None else _f64(base_rhs)
         tb = None if theta_base is None else _f64(theta_base)
+        self._keep = (pm, L, U)
         _check(self._lib.gpcg_setup(C.byref(h), self.n_bus, self.m, _ip(self.br_from), _ip(self.br_to),
-                                    _fp(self.x), C.byref(a), C.byref(l), C.byref(u), _fp(rhs), _fp(tb),
+                                    _fp(self.x), C.byref(a), l, u, _fp(rhs), _fp(tb),
                                     C.byref(opt), C.c_void_p(self.stream.cuda_stream)))
         self._h = h
+        self.perm = np.zeros(self.n_bus - 1, np.int32)
+        _check(self._lib.gpcg_get_perm(self._h, _ip(self.perm)))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -255,6 +287,12 @@ class Context:
         I = Info()
         _check(self._lib.gpcg_get_info(self._h, C.byref(I)))
         return I.as_dict()
+
+    def bridge_flags(self) -> np.ndarray:
+        """gpcg_bridge_flags: bool[m]."""
+        isb = np.zeros(self.m, np.uint8)
+        _check(self._lib.gpcg_bridge_flags(self._h, isb.ctypes.data_as(_u8p)))
+        return isb.astype(bool)
 
     def base(self):
         """(is_bridge[m] bool, theta_base[n_bus]) as NumPy arrays."""

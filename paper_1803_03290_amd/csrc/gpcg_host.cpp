@@ -159,6 +159,74 @@ int assemble(int n_bus, int m, const int32_t *from, const int32_t *to, const dou
     return (int)col.size();
 }
 
+// Reverse Cuthill-McKee order of the buses other than the slack (the slack
+// and its branches leave the reduced system).  Every connected piece starts
+// at its bus of least degree (ties by bus number); a breadth-first search
+// appends each bus's unvisited neighbours by increasing degree (ties by bus
+// number), and the whole sequence is reversed.  (A pseudo-peripheral start
+// gave a slightly smaller bandwidth but longer triangular dependency chains
+// and more PCG iterations on the synthetic grids.)  perm[k] is the bus of
+// reduced row k.
+std::vector<int32_t> rcm_order(int n_bus, int m, const int32_t *from, const int32_t *to) {
+    std::vector<std::vector<int>> adj(n_bus);
+    for (int e = 0; e < m; ++e) {
+        if (from[e] == 0 || to[e] == 0) continue;
+        adj[from[e]].push_back(to[e]);
+        adj[to[e]].push_back(from[e]);
+    }
+    std::vector<int> deg(n_bus, 0);
+    for (int v = 1; v < n_bus; ++v) {
+        auto &a = adj[v];
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+        deg[v] = (int)a.size();
+    }
+    auto lighter = [&](int x, int y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; };
+    for (int v = 1; v < n_bus; ++v) std::sort(adj[v].begin(), adj[v].end(), lighter);
+    std::vector<char> seen(n_bus, 0), mark(n_bus, 0);
+    std::vector<int> piece, seq;
+    seq.reserve(n_bus - 1);
+    for (int s0 = 1; s0 < n_bus; ++s0) {
+        if (mark[s0]) continue;
+        // the piece of s0 and its lightest bus
+        piece.assign(1, s0);
+        seen[s0] = 1;
+        for (size_t t = 0; t < piece.size(); ++t)
+            for (int w : adj[piece[t]])
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    piece.push_back(w);
+                }
+        const int root = *std::min_element(piece.begin(), piece.end(), lighter);
+        size_t head = seq.size();
+        seq.push_back(root);
+        mark[root] = 1;
+        while (head < seq.size()) {
+            const int v = seq[head++];
+            for (int w : adj[v])
+                if (!mark[w]) {
+                    mark[w] = 1;
+                    seq.push_back(w);
+                }
+        }
+    }
+    std::reverse(seq.begin(), seq.end());
+    return std::vector<int32_t>(seq.begin(), seq.end());
+}
+
+// Check that perm holds every bus 1 .. n_bus - 1 once; returns inv with
+// inv[perm[k]] = k + 1 (the internal bus) and inv[0] = 0.
+std::vector<int32_t> invert_perm(int n_bus, const int32_t *perm) {
+    std::vector<int32_t> inv(n_bus, -1);
+    inv[0] = 0;
+    for (int k = 0; k < n_bus - 1; ++k) {
+        const int b = perm[k];
+        if (b < 1 || b >= n_bus || inv[b] >= 0) fail(GPCG_E_ARG, "perm must hold each bus 1 .. n_bus - 1 once");
+        inv[b] = k + 1;
+    }
+    return inv;
+}
+
 // Zero-fill incomplete LU, IKJ order (Saad, Alg. 10.4), with a dense
 // column-to-position map of the current row.
 void ilu0(const gpcg_csr &A, std::vector<double> &F, std::vector<int> &diagpos) {
@@ -550,7 +618,11 @@ struct gpcg_context {
     int nnz_a = 0, nnz_l = 0, nnz_u = 0;
     DevBuf<int32_t> a_rowptr, a_col, l_rowptr, l_col, u_rowptr, u_col;
     DevBuf<double> a_val, l_val, u_val, u_invdiag;
+    // the matrix side in internal buses (row i = internal bus i + 1); the
+    // bus side (flows, overload, power flow) in the caller's numbering
     DevBuf<int32_t> br_from, br_to, pre_row, pre_bus, isl_lo, isl_hi;
+    DevBuf<int32_t> cbr_from, cbr_to, cpre_bus, bus_map;  // bus_map: internal -> caller (none: identity)
+    std::vector<int32_t> perm, inv;                       // row -> caller's bus, caller's bus -> internal (empty: identity)
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
     DevBuf<int32_t> queue;               // the PCG launch's queue counter
@@ -601,8 +673,8 @@ struct gpcg_context {
         const int wp = ring_needed(P, hA, false, max_ring);
         if (wp < 0)
             fail(GPCG_E_UNSUPPORTED, "the matrix bandwidth needs a larger LDS ring than a wavefront may use; "
-                                     "number the buses in a banded order (e.g. reverse Cuthill-McKee) or use a "
-                                     "smaller block");
+                                     "give a banded row order (gpcg_options.perm, e.g. from gpcg_rcm) or set "
+                                     "gpcg_options.reorder, or use a smaller block");
         for (int look_try = look;; look_try /= 2) {
             Schedule F = build_schedule(n_r, R, look_try, deps_f);
             Schedule B = build_schedule(n_r, R, look_try, deps_b);
@@ -622,7 +694,8 @@ struct gpcg_context {
             }
             if (look_try <= R)
                 fail(GPCG_E_UNSUPPORTED, "the factors' bandwidth needs a larger LDS ring than a wavefront may use; "
-                                         "number the buses in a banded order (e.g. reverse Cuthill-McKee)");
+                                         "give a banded row order (gpcg_options.perm, e.g. from gpcg_rcm) or set "
+                                         "gpcg_options.reorder");
         }
         slot = std::move(D);
         return *slot;
@@ -635,6 +708,7 @@ struct gpcg_context {
         p.n_bus = n_bus;
         p.m = m;
         p.kind = kind;
+        p.bus_map = bus_map.p;
         p.fwd = D.f.view();
         p.bwd = D.b.view();
         p.prod = D.p.view();
@@ -673,6 +747,8 @@ struct gpcg_context {
     }
 
     size_t ws_slot(int S_) const { return (size_t)gpcg::kVectors * gpcg::vec_stride(n_r, S_); }
+
+    int internal_bus(int k) const { return inv.empty() ? k : inv[k]; }
 };
 
 namespace {
@@ -783,7 +859,7 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     // residual of the base state for this right-hand side, in double-double
     if (!rhs_cols)
         hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs,
-                                             h->rho_b.p, h->stream),
+                                             h->bus_map.p, h->rho_b.p, h->stream),
                   "base residual");
     gpcg::PcgParams p = h->params(D, outages, n_out, rhs, tol, max_iter, iters_out, status_out);
     p.ws = w.ws;
@@ -818,6 +894,9 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     o.m = h->m;
     o.kind = h->kind;
     o.n_out = n_out;
+    o.bus_map = h->bus_map.p;
+    o.cbr_from = h->cbr_from.p;
+    o.cbr_to = h->cbr_to.p;
     o.a_rowptr = h->a_rowptr.p;
     o.a_col = h->a_col.p;
     o.a_val = h->a_val.p;
@@ -880,7 +959,7 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
     h->base_iters = 0;
     for (int pass = 0; pass < 6; ++pass) {
         hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, rhs.p,
-                                             h->rho_b.p, h->stream),
+                                             nullptr, h->rho_b.p, h->stream),
                   "base residual");
         double rr = 0.0;
         hip_check(gpcg::launch_sumsq(h->n_r, h->rho_b.p, dsum.p, h->stream), "sumsq");
@@ -894,6 +973,7 @@ void base_solve(gpcg_context *h, const double *rhs_host, int max_iter) {
                                  h->stream),
                   "copy");
         gpcg::PcgParams p = h->params(D, out1.p, 1, rhs.p, 1e-13, max_iter, it.p, st.p);
+        p.bus_map = nullptr;  // the correction's right-hand side and result are by internal bus
         p.rhs_cols = rho_bus.p;
         p.rhs_ld = n_bus;
         p.ws = w.ws;
@@ -1093,7 +1173,7 @@ void batch_enqueue(gpcg_batch *b) {
         gpcg_context *h = G->ctx;
         if (G->n_out == 0 || h->zero_start) continue;
         hip_check(gpcg::launch_base_residual(h->n_r, h->a_rowptr.p, h->a_col.p, h->a_val.p, h->theta_b.p, G->rhs,
-                                             G->rho_b.p, b->stream),
+                                             h->bus_map.p, G->rho_b.p, b->stream),
                   "base residual");
     }
     hip_check(gpcg::launch_pcg_multi(b->params.p, (int)b->g.size(), b->S, b->n_waves, b->ring, b->stream),
@@ -1107,6 +1187,9 @@ void batch_enqueue(gpcg_batch *b) {
         o.m = h->m;
         o.kind = h->kind;
         o.n_out = G->n_out;
+        o.bus_map = h->bus_map.p;
+        o.cbr_from = h->cbr_from.p;
+        o.cbr_to = h->cbr_to.p;
         o.a_rowptr = h->a_rowptr.p;
         o.a_col = h->a_col.p;
         o.a_val = h->a_val.p;
@@ -1139,18 +1222,46 @@ extern "C" {
 const char *gpcg_last_error(void) { return g_last_error.c_str(); }
 
 int gpcg_assemble(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, const double *x,
-                  const double *shunt, int32_t *rowptr, int32_t *col, double *val, int32_t cap, int32_t *nnz_out) {
+                  const double *shunt, const int32_t *perm, int32_t *rowptr, int32_t *col, double *val, int32_t cap,
+                  int32_t *nnz_out) {
     return guarded([&] {
         if (!x || !rowptr || !col || !val || !nnz_out) fail(GPCG_E_ARG, "NULL argument");
         check_branches(n_bus, m, from, to, x);
-        std::vector<int32_t> rp, c;
-        std::vector<double> v;
-        const int nnz = assemble(n_bus, m, from, to, x, shunt, rp, c, v);
+        std::vector<int32_t> rp, c, f2, t2;
+        std::vector<double> v, sh2;
+        const int32_t *ff = from, *tt = to;
+        const double *sh = shunt;
+        if (perm) {  // rows in perm's order: relabel the buses by their row
+            const std::vector<int32_t> inv = invert_perm(n_bus, perm);
+            f2.resize(m);
+            t2.resize(m);
+            for (int e = 0; e < m; ++e) {
+                f2[e] = inv[from[e]];
+                t2[e] = inv[to[e]];
+            }
+            ff = f2.data();
+            tt = t2.data();
+            if (shunt) {
+                sh2.assign(n_bus, 0.0);
+                for (int k = 0; k < n_bus; ++k) sh2[inv[k]] = shunt[k];
+                sh = sh2.data();
+            }
+        }
+        const int nnz = assemble(n_bus, m, ff, tt, x, sh, rp, c, v);
         if (nnz > cap) fail(GPCG_E_ARG, "output capacity too small");
         std::copy(rp.begin(), rp.end(), rowptr);
         std::copy(c.begin(), c.end(), col);
         std::copy(v.begin(), v.end(), val);
         *nnz_out = nnz;
+    });
+}
+
+int gpcg_rcm(int32_t n_bus, int32_t m, const int32_t *from, const int32_t *to, int32_t *perm) {
+    return guarded([&] {
+        if (!perm) fail(GPCG_E_ARG, "perm is NULL");
+        check_branches(n_bus, m, from, to, nullptr);
+        const std::vector<int32_t> p = rcm_order(n_bus, m, from, to);
+        std::copy(p.begin(), p.end(), perm);
     });
 }
 
@@ -1208,14 +1319,84 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         check_branches(n_bus, m, br_from, br_to, br_x);
         const int nr = n_bus - 1;
         check_csr(A, "A", nr);
-        check_csr(L, "L", nr);
-        check_csr(U, "U", nr);
         if (!theta_base && !base_rhs) fail(GPCG_E_ARG, "either base_rhs or theta_base is required");
         gpcg_options o{};
         if (opt) o = *opt;
         if (o.kind != GPCG_KIND_BP && o.kind != GPCG_KIND_BPP) fail(GPCG_E_ARG, "unknown kind");
         const int S = o.block ? o.block : 64;
         if (S < 1 || S > 64 || (S & (S - 1))) fail(GPCG_E_ARG, "block must be a power of two in [1, 64]");
+        if ((L == nullptr) != (U == nullptr)) fail(GPCG_E_ARG, "give both factors L and U, or neither");
+        if (o.reorder && o.perm) fail(GPCG_E_ARG, "give perm or ask for reorder, not both");
+        if (o.reorder && L) fail(GPCG_E_ARG, "reorder forms its own factors: L and U must be NULL");
+        // The row order: the caller's perm, the library's reverse Cuthill-McKee
+        // order (reorder; A is then given in bus order and permuted here), or
+        // the bus order.  inv turns a caller's bus into its internal bus.
+        std::vector<int32_t> perm, inv;
+        if (o.perm) {
+            perm.assign(o.perm, o.perm + nr);
+            inv = invert_perm(n_bus, o.perm);
+        } else if (o.reorder) {
+            perm = rcm_order(n_bus, m, br_from, br_to);
+            inv = invert_perm(n_bus, perm.data());
+        }
+        CsrH Ah, Lh, Uh;
+        if (o.reorder) {
+            std::vector<std::vector<std::pair<int, double>>> rows(nr);
+            for (int i = 0; i < nr; ++i)
+                for (int e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e)
+                    rows[inv[i + 1] - 1].push_back({inv[A->col[e] + 1] - 1, A->val[e]});
+            Ah.rowptr.assign(nr + 1, 0);
+            for (int i = 0; i < nr; ++i) {
+                std::sort(rows[i].begin(), rows[i].end());
+                for (auto &cv : rows[i]) {
+                    Ah.col.push_back(cv.first);
+                    Ah.val.push_back(cv.second);
+                }
+                Ah.rowptr[i + 1] = (int32_t)Ah.col.size();
+            }
+        } else {
+            Ah.rowptr.assign(A->rowptr, A->rowptr + nr + 1);
+            Ah.col.assign(A->col, A->col + A->nnz);
+            Ah.val.assign(A->val, A->val + A->nnz);
+        }
+        gpcg_csr Av{nr, (int32_t)Ah.col.size(), Ah.rowptr.data(), Ah.col.data(), Ah.val.data()};
+        A = &Av;
+        if (!L) {  // the base-case ILU(0) of A in row order (Section IV.B)
+            std::vector<double> F;
+            std::vector<int> dp;
+            ilu0(Av, F, dp);
+            Lh.rowptr.assign(nr + 1, 0);
+            Uh.rowptr.assign(nr + 1, 0);
+            for (int i = 0; i < nr; ++i) {
+                for (int e = Ah.rowptr[i]; e < Ah.rowptr[i + 1]; ++e) {
+                    CsrH &T = Ah.col[e] < i ? Lh : Uh;
+                    T.col.push_back(Ah.col[e]);
+                    T.val.push_back(F[e]);
+                }
+                Lh.rowptr[i + 1] = (int32_t)Lh.col.size();
+                Uh.rowptr[i + 1] = (int32_t)Uh.col.size();
+            }
+        } else {
+            check_csr(L, "L", nr);
+            check_csr(U, "U", nr);
+            Lh.rowptr.assign(L->rowptr, L->rowptr + nr + 1);
+            Lh.col.assign(L->col, L->col + L->nnz);
+            Lh.val.assign(L->val, L->val + L->nnz);
+            Uh.rowptr.assign(U->rowptr, U->rowptr + nr + 1);
+            Uh.col.assign(U->col, U->col + U->nnz);
+            Uh.val.assign(U->val, U->val + U->nnz);
+        }
+        gpcg_csr Lv{nr, (int32_t)Lh.col.size(), Lh.rowptr.data(), Lh.col.data(), Lh.val.data()};
+        gpcg_csr Uv{nr, (int32_t)Uh.col.size(), Uh.rowptr.data(), Uh.col.data(), Uh.val.data()};
+        L = &Lv;
+        U = &Uv;
+        // branch endpoints as internal buses (the caller's when no perm)
+        std::vector<int32_t> ifrom(br_from, br_from + m), ito(br_to, br_to + m);
+        if (!inv.empty())
+            for (int e = 0; e < m; ++e) {
+                ifrom[e] = inv[br_from[e]];
+                ito[e] = inv[br_to[e]];
+            }
         // factor shapes: L strictly lower, U upper with a positive diagonal first
         std::vector<double> invdiag(nr);
         std::vector<int32_t> us_rowptr(nr + 1, 0), us_col;
@@ -1264,7 +1445,9 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->nnz_a = A->nnz;
         h->nnz_l = L->nnz;
         h->nnz_u = U->nnz;
-        h->topo = topology(n_bus, m, br_from, br_to);
+        h->perm = perm;
+        h->inv = inv;
+        h->topo = topology(n_bus, m, ifrom.data(), ito.data());
         // dependency lists for the schedules (backward on mirrored indices)
         h->deps_f.assign(nr, {});
         h->deps_b.assign(nr, {});
@@ -1297,14 +1480,26 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->u_invdiag.upload(invdiag.data(), nr, st);
         std::vector<double> b(m);
         for (int e = 0; e < m; ++e) b[e] = 1.0 / br_x[e];
-        h->br_from.upload(br_from, m, st);
-        h->br_to.upload(br_to, m, st);
+        h->br_from.upload(ifrom.data(), m, st);
+        h->br_to.upload(ito.data(), m, st);
+        h->cbr_from.upload(br_from, m, st);
+        h->cbr_to.upload(br_to, m, st);
         h->br_x.upload(br_x, m, st);
         h->br_b.upload(b.data(), m, st);
         std::vector<int32_t> prerow(nr);
         for (int i = 0; i < nr; ++i) prerow[i] = h->topo.pre[i + 1];
         h->pre_row.upload(prerow.data(), nr, st);
         h->pre_bus.upload(h->topo.pre.data(), n_bus, st);
+        {  // pre-order numbers by the caller's bus, and internal bus -> caller's bus
+            std::vector<int32_t> cpre(n_bus);
+            for (int k = 0; k < n_bus; ++k) cpre[k] = h->topo.pre[inv.empty() ? k : inv[k]];
+            h->cpre_bus.upload(cpre.data(), n_bus, st);
+            if (!perm.empty()) {
+                std::vector<int32_t> map(n_bus, 0);
+                for (int k = 0; k < nr; ++k) map[k + 1] = perm[k];
+                h->bus_map.upload(map.data(), n_bus, st);
+            }
+        }
         h->isl_lo.upload(h->topo.lo.data(), m, st);
         h->isl_hi.upload(h->topo.hi.data(), m, st);
         {  // branches incident to each bus, for gathers over a bus's branches
@@ -1328,13 +1523,15 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         hip_check(hipStreamSynchronize(st), "setup upload");
         h->schedule_for(S);
         if (theta_base) {
-            std::vector<double> t(theta_base, theta_base + n_bus);
-            t[0] = 0.0;
+            std::vector<double> t(n_bus, 0.0);  // by internal bus
+            for (int k = 1; k < n_bus; ++k) t[h->internal_bus(k)] = theta_base[k];
             h->theta_b.upload(t.data(), n_bus, st);
             h->theta_b_host = t;
             hip_check(hipStreamSynchronize(st), "theta upload");
         } else {
-            base_solve(h.get(), base_rhs, o.base_max_iter > 0 ? o.base_max_iter : 20000);
+            std::vector<double> r(n_bus, 0.0);
+            for (int k = 0; k < n_bus; ++k) r[h->internal_bus(k)] = base_rhs[k];
+            base_solve(h.get(), r.data(), o.base_max_iter > 0 ? o.base_max_iter : 20000);
         }
         *out = h.release();
     });
@@ -1379,7 +1576,22 @@ int gpcg_get_base(gpcg_t h, uint8_t *is_bridge, double *theta_base) {
     return guarded([&] {
         if (!h) fail(GPCG_E_ARG, "NULL context");
         if (is_bridge) std::copy(h->topo.is_bridge.begin(), h->topo.is_bridge.end(), is_bridge);
-        if (theta_base) std::copy(h->theta_b_host.begin(), h->theta_b_host.end(), theta_base);
+        if (theta_base)
+            for (int k = 0; k < h->n_bus; ++k) theta_base[k] = h->theta_b_host[h->internal_bus(k)];
+    });
+}
+
+int gpcg_bridge_flags(gpcg_t h, uint8_t *is_bridge) {
+    return guarded([&] {
+        if (!h || !is_bridge) fail(GPCG_E_ARG, "NULL argument");
+        std::copy(h->topo.is_bridge.begin(), h->topo.is_bridge.end(), is_bridge);
+    });
+}
+
+int gpcg_get_perm(gpcg_t h, int32_t *perm) {
+    return guarded([&] {
+        if (!h || !perm) fail(GPCG_E_ARG, "NULL argument");
+        for (int k = 0; k < h->n_r; ++k) perm[k] = h->perm.empty() ? k + 1 : h->perm[k];
     });
 }
 
@@ -1442,12 +1654,12 @@ int gpcg_overload_gradients(gpcg_t h, int32_t n_out, const int32_t *outages, con
         o.m = h->m;
         o.n_out = n_out;
         o.kappa = kappa;
-        o.br_from = h->br_from.p;
-        o.br_to = h->br_to.p;
+        o.br_from = h->cbr_from.p;  // every array of this call is by the caller's bus
+        o.br_to = h->cbr_to.p;
         o.br_x = h->br_x.p;
         o.inc_ptr = h->inc_ptr.p;
         o.inc_br = h->inc_br.p;
-        o.pre_bus = h->pre_bus.p;
+        o.pre_bus = h->cpre_bus.p;
         o.isl_lo = h->isl_lo.p;
         o.isl_hi = h->isl_hi.p;
         o.outages = outages;
@@ -1499,7 +1711,7 @@ int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, cons
             std::vector<double> d(bpp->n_bus, 0.0);
             for (int i = 0; i < bpp->n_r; ++i)
                 for (int e = bpp->hA.rowptr[i]; e < bpp->hA.rowptr[i + 1]; ++e)
-                    if (bpp->hA.col[e] == i) d[i + 1] = bpp->hA.val[e];
+                    if (bpp->hA.col[e] == i) d[bpp->perm.empty() ? i + 1 : bpp->perm[i]] = bpp->hA.val[e];
             bpp->diag_bus.upload(d.data(), d.size(), bpp->stream);
             hip_check(hipStreamSynchronize(bpp->stream), "diagonal upload");
         }
@@ -1518,12 +1730,12 @@ int gpcg_fdpf(gpcg_t bp, gpcg_t bpp, int32_t n_out, const int32_t *outages, cons
         f.n_bus = bp->n_bus;
         f.m = bp->m;
         f.n_out = n_out;
-        f.br_from = bp->br_from.p;
-        f.br_to = bp->br_to.p;
+        f.br_from = bp->cbr_from.p;  // every array of this call is by the caller's bus
+        f.br_to = bp->cbr_to.p;
         f.br_b = bp->br_b.p;
         f.inc_ptr = bp->inc_ptr.p;
         f.inc_br = bp->inc_br.p;
-        f.pre_bus = bp->pre_bus.p;
+        f.pre_bus = bp->cpre_bus.p;
         f.isl_lo = bp->isl_lo.p;
         f.isl_hi = bp->isl_hi.p;
         f.outages = outages;

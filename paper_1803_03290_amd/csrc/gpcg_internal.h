@@ -65,10 +65,18 @@ constexpr int kBwdRowBits = 20;                      // row and pre-order fields
 constexpr int kBwdRowMask = (1 << kBwdRowBits) - 1;  // also the "none" pre-order number
 constexpr int kBwdMaxRing = 2048;                    // ring rows of the backward solve (slot + 2 < 2^12)
 
+// Buses are numbered internally in the order of the reduced rows: row i is
+// internal bus i + 1, the slack is 0.  bus_map (device, n_bus; NULL when the
+// caller's numbering is the internal one) turns an internal bus into the
+// caller's bus, which numbers every bus-indexed array the caller passes or
+// receives.
+__host__ __device__ __forceinline__ int caller_bus(const int32_t *bus_map, int k) { return bus_map ? bus_map[k] : k; }
+
 // Everything one launch of the persistent PCG kernel needs.  All pointers
-// are device memory.  Reduced row i is bus i + 1.
+// are device memory.  Reduced row i is internal bus i + 1.
 struct PcgParams {
     int n_r, n_bus, m, kind;
+    const int32_t *bus_map;  // internal bus -> caller's bus (NULL: the same)
     Program fwd;   // y = L^-1 r  (rows in a dependency-respecting order)
     Program bwd;   // z = U^-1 y
     Program prod;  // p = z + beta p, delta += alpha p_old, q = A_c p (natural order, R rows per step)
@@ -81,10 +89,10 @@ struct PcgParams {
     // base state and its double-double residual for this right-hand side
     const double *theta_b;  // n_bus, slack 0
     const double *rho_b;    // n_r: rhs - A theta_b
-    const double *rhs;      // n_bus
+    const double *rhs;      // n_bus, caller's numbering
     // per-scenario right-hand sides (NULL: rhs above with the warm start):
-    // scenario j solves A_c x = rhs_cols[j * rhs_ld + bus] from x = 0, with
-    // no re-dispatch
+    // scenario j solves A_c x = rhs_cols[j * rhs_ld + bus] (caller's bus)
+    // from x = 0, with no re-dispatch
     const double *rhs_cols;
     int rhs_ld;
     int zero_start;  // 1: start from x = 0 (r0 = P'_M), the result is theta itself
@@ -102,7 +110,8 @@ struct PcgParams {
     double *ws;
     size_t ws_slot;
     // results, written when a column stops: x = (theta_b if add_base) + delta
-    // on the main system [n_out x n_bus], steps, status, re-dispatch factor
+    // on the main system [n_out x n_bus, caller's numbering], steps, status,
+    // re-dispatch factor
     double *x_out;
     int add_base;
     int32_t *iters_out, *status_out;
@@ -113,13 +122,15 @@ struct PcgParams {
 // flags, flows, true residuals.
 struct OutParams {
     int n_r, n_bus, m, kind, n_out;
+    const int32_t *bus_map;            // internal bus -> caller's bus (NULL: the same)
+    const int32_t *cbr_from, *cbr_to;  // branch endpoints in the caller's numbering (flows)
     const int32_t *a_rowptr, *a_col;
     const double *a_val;
     const int32_t *br_from, *br_to;
     const double *br_x, *br_b;
-    const int32_t *pre_bus;  // n_bus
+    const int32_t *pre_bus;  // n_bus, by internal bus
     const int32_t *isl_lo, *isl_hi;
-    const double *theta_b, *rhs;
+    const double *theta_b, *rhs;  // theta_b internal, rhs caller's numbering
     const double *rhs_cols;  // per-scenario right-hand sides (then x = delta, no base state added)
     int rhs_ld;
     int add_base;  // 1: x = theta_b + delta (warm start from the base state)
@@ -205,8 +216,10 @@ hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_wa
 // wavefronts of the PCG kernel at block S that fit the device at once
 int pcg_max_waves(int S, int ring_rows);
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st);
+// rho = rhs - A theta_b (theta_b internal; rhs by bus_map, NULL: internal)
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
-                                const double *theta_b, const double *rhs, double *rho, hipStream_t st);
+                                const double *theta_b, const double *rhs, const int32_t *bus_map, double *rho,
+                                hipStream_t st);
 // theta_b[k] += x[k] for the buses k >= 1
 hipError_t launch_base_accumulate(int n_bus, double *theta_b, const double *x, hipStream_t st);
 // q = A_c p over ncols / S tiles of n_r x S (bw: bandwidth of A).  Rows are

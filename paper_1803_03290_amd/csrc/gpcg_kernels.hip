@@ -47,8 +47,8 @@ __global__ void island_out_kernel(OutParams p) {
         lo = p.isl_lo[c];
         hi = p.isl_hi[c];
     }
-    const bool in = (k > 0) && in_interval(p.pre_bus[k], lo, hi);
-    p.island_out[(size_t)s * p.n_bus + k] = in ? 1 : 0;
+    const bool in = (k > 0) && in_interval(p.pre_bus[k], lo, hi);  // k: internal bus
+    p.island_out[(size_t)s * p.n_bus + caller_bus(p.bus_map, k)] = in ? 1 : 0;
 }
 
 // Branch flows (theta_f - theta_t) / x_e; the outaged branch carries 0 and
@@ -60,7 +60,7 @@ __global__ void flows_out_kernel(OutParams p) {
     const int c = p.outages[s];
     const double *th = p.x_out + (size_t)s * p.n_bus;
     double f = 0.0;
-    if (e != c && c >= -1 && c < p.m) f = (th[p.br_from[e]] - th[p.br_to[e]]) / p.br_x[e];
+    if (e != c && c >= -1 && c < p.m) f = (th[p.cbr_from[e]] - th[p.cbr_to[e]]) / p.br_x[e];
     p.flows_out[(size_t)s * p.m + e] = f;
 }
 
@@ -84,15 +84,19 @@ __global__ void __launch_bounds__(256) resid_kernel(OutParams p) {
     }
     const double gfac = p.gfac[s];
     const double *th = p.x_out + (size_t)s * p.n_bus;
-    const double thf = (ic >= 0) ? th[ic + 1] : 0.0, tht = (jc >= 0) ? th[jc + 1] : 0.0;
+    const int32_t *bm = p.bus_map;
+    const double thf = (ic >= 0) ? th[caller_bus(bm, ic + 1)] : 0.0;
+    const double tht = (jc >= 0) ? th[caller_bus(bm, jc + 1)] : 0.0;
     double rr = 0.0, bb = 0.0;
     if (!bad) {
         for (int i = threadIdx.x; i < p.n_r; i += blockDim.x) {
             if (in_interval(p.pre_bus[i + 1], lo, hi)) continue;
-            const double Pk = p.rhs_cols ? p.rhs_cols[(size_t)s * p.rhs_ld + i + 1] : p.rhs[i + 1];
+            const int k = caller_bus(bm, i + 1);
+            const double Pk = p.rhs_cols ? p.rhs_cols[(size_t)s * p.rhs_ld + k] : p.rhs[k];
             const double b = Pk + ((gfac != 0.0 && Pk > 0.0) ? Pk * gfac : 0.0);
             double h = b, l = 0.0;
-            for (int e = p.a_rowptr[i]; e < p.a_rowptr[i + 1]; ++e) dd_fma(h, l, -p.a_val[e], th[p.a_col[e] + 1]);
+            for (int e = p.a_rowptr[i]; e < p.a_rowptr[i + 1]; ++e)
+                dd_fma(h, l, -p.a_val[e], th[caller_bus(bm, p.a_col[e] + 1)]);
             if (i == ic) {
                 dd_fma(h, l, bc, thf);
                 dd_fma(h, l, -bc, tht);
@@ -122,13 +126,15 @@ __global__ void __launch_bounds__(256) resid_kernel(OutParams p) {
     }
 }
 
-// rho = rhs - A theta_b per reduced row, in double-double, rounded once.
+// rho = rhs - A theta_b per reduced row, in double-double, rounded once
+// (theta_b by internal bus, rhs by the caller's).
 __global__ void base_residual_kernel(int n_r, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                      const double *__restrict__ val, const double *__restrict__ theta_b,
-                                     const double *__restrict__ rhs, double *__restrict__ rho) {
+                                     const double *__restrict__ rhs, const int32_t *__restrict__ bus_map,
+                                     double *__restrict__ rho) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_r) return;
-    double h = rhs[i + 1], l = 0.0;
+    double h = rhs[caller_bus(bus_map, i + 1)], l = 0.0;
     for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) dd_fma(h, l, -val[e], theta_b[col[e] + 1]);
     rho[i] = h + l;
 }
@@ -725,10 +731,11 @@ hipError_t launch_outputs(const OutParams &prm, hipStream_t st) {
 }
 
 hipError_t launch_base_residual(int n_r, const int32_t *rowptr, const int32_t *col, const double *val,
-                                const double *theta_b, const double *rhs, double *rho, hipStream_t st) {
+                                const double *theta_b, const double *rhs, const int32_t *bus_map, double *rho,
+                                hipStream_t st) {
     if (n_r <= 0) return hipSuccess;
     hipLaunchKernelGGL(base_residual_kernel, dim3((n_r + 255) / 256), dim3(256), 0, st, n_r, rowptr, col, val, theta_b,
-                       rhs, rho);
+                       rhs, bus_map, rho);
     return hipGetLastError();
 }
 

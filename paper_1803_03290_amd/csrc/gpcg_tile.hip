@@ -551,10 +551,10 @@ __device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T,
     const bool cols = p.rhs_cols != nullptr;
     double rr = 0.0, bb = 0.0;
     if (cols) {
-        const double *b = p.rhs_cols + (size_t)(take ? scen : 0) * p.rhs_ld + 1;
+        const double *b = p.rhs_cols + (size_t)(take ? scen : 0) * p.rhs_ld;
         for (int i = rs; i < nr; i += R) {
             if (take) {
-                const double r0 = !in_interval(p.pre_row[i], c.lo, c.hi) ? b[i] : 0.0;
+                const double r0 = !in_interval(p.pre_row[i], c.lo, c.hi) ? b[caller_bus(p.bus_map, i + 1)] : 0.0;
                 rr += r0 * r0;
                 const unsigned o = row_off<S>(T, i, sc);
                 xp_put(T, o, 0.0, 0.0);
@@ -566,7 +566,7 @@ __device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T,
         double dP = 0.0, Sg = 0.0;
         for (int i = rs; i < nr; i += R) {
             if (take) {
-                const double Pk = p.rhs[i + 1];
+                const double Pk = p.rhs[caller_bus(p.bus_map, i + 1)];
                 if (in_interval(p.pre_row[i], c.lo, c.hi))
                     dP += Pk;
                 else if (Pk > 0.0)
@@ -584,7 +584,7 @@ __device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T,
             if (take) {
                 double r0 = 0.0;
                 if (!in_interval(p.pre_row[i], c.lo, c.hi)) {
-                    const double Pk = p.rhs[i + 1];
+                    const double Pk = p.rhs[caller_bus(p.bus_map, i + 1)];
                     const double dPk = (c.gfac != 0.0 && Pk > 0.0) ? Pk * c.gfac : 0.0;
                     const double b = Pk + dPk;
                     if (p.zero_start) {
@@ -628,7 +628,7 @@ __device__ __forceinline__ void column_retire(const PcgParams &p, const Tile &T,
         double v = 0.0;
         if (!in_interval(p.pre_row[i], c.lo, c.hi))
             v = (p.add_base ? p.theta_b[i + 1] : 0.0) + xp_get(T, row_off<S>(T, i, sc)).x;
-        x[i + 1] = v;
+        x[caller_bus(p.bus_map, i + 1)] = v;
     }
     if (rs == 0) {
         x[0] = 0.0;

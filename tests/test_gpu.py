@@ -47,12 +47,30 @@ def gp():
     return gp
 
 
-def _ctx(gp, g, block=64, kind=0, shunt=None, rhs=None, A=None):
+def _ctx(gp, g, block=64, kind=0, shunt=None, rhs=None, perm="harness"):
+    """A context on grid g (buses in the generator's numbering).  Its rows
+    follow the harness's reverse Cuthill-McKee order (SciPy's, the order
+    the oracle's iteration counts use), the library's own ("rcm"), or a
+    given order."""
     base = g.P if rhs is None else rhs
-    if A is not None:
-        A = A.tocsr()
-        A = gp.binding.Csr(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
-    return gp.Context(g.n, g.br_from, g.br_to, g.x, base, block=block, kind=kind, shunt=shunt, A=A)
+    if isinstance(perm, str) and perm == "harness":
+        perm = gridgen.rcm_perm(g)
+    return gp.Context(g.n, g.br_from, g.br_to, g.x, base, block=block, kind=kind, shunt=shunt, perm=perm)
+
+
+def _oracle_rows(g, shunt=None, rhs=None):
+    """The oracle's system with the buses relabelled in the harness's row
+    order (what the device's factors see), for iteration counts: the
+    relabelled grid, its base state and matrix, ILU(0) factors, and the
+    map old[new bus] = generator bus.  Outage ids are unchanged."""
+    perm = gridgen.rcm_perm(g)
+    gr = gridgen.renumber(g, perm)
+    old = np.r_[0, perm].astype(np.int64)
+    sh = None if shunt is None else np.asarray(shunt)[old]
+    b = None if rhs is None else np.asarray(rhs)[old]
+    thb, A = oracle.base_case(gr, rhs=b, shunt=sh)
+    L, U = oracle.ilu0(A)
+    return gr, thb, A, L, U, old
 
 
 def _run(gp, ctx, g, outages, rhs=None, tol=1e-12, max_iter=20000, plain=False):
@@ -121,13 +139,12 @@ def test_grid200_all_outages(gp, grids, block):
 
 def test_grid200_iterations_match_textbook_pcg(gp, grids):
     g = grids["grid200"]
-    thb, A = oracle.base_case(g)
-    L, U = oracle.ilu0(A)
+    gr, thb, A, L, U, _ = _oracle_rows(g)
     ctx = _ctx(gp, g, block=64)
     outs = list(range(g.m))
     res = _run(gp, ctx, g, outs, tol=1e-12)
     for s, c in enumerate(outs):
-        p = oracle.scenario_pcg(g, c, A, L, U, thb, tol=1e-12)
+        p = oracle.scenario_pcg(gr, c, A, L, U, thb, tol=1e-12)
         assert _iters_close(res["iters"][s], p["iters"]), (c, res["iters"][s], p["iters"])
 
 
@@ -236,14 +253,14 @@ def test_grid2k_all_outages_batched(gp, grids, block, tol):
     residual bar) 7 of the 2,800 outages end 1.0e-8 to 1.4e-8 rad from the
     direct solution."""
     g = grids["grid2k"]
-    thb, A = oracle.base_case(g)
-    L, U = oracle.ilu0(A)
+    _, A = oracle.base_case(g)
+    gr, thb, Ar, L, U, _ = _oracle_rows(g)
     ctx = _ctx(gp, g, block=block)
     outs = np.arange(g.m)
     res = _run(gp, ctx, g, outs, tol=tol)
     _check_all(g, A, outs, res, gp)
     for c in np.sort(np.random.default_rng(7).choice(g.m, 12, replace=False)):
-        p = oracle.scenario_pcg(g, int(c), A, L, U, thb, tol=tol)
+        p = oracle.scenario_pcg(gr, int(c), Ar, L, U, thb, tol=tol)
         assert _iters_close(res["iters"][c], p["iters"]), (c, res["iters"][c], p["iters"])
 
 
@@ -264,6 +281,57 @@ def test_grid10k_all_outages(gp, grids):
     outs = np.arange(g.m)
     res = _run(gp, ctx, g, outs, tol=1e-12)
     _check_all(g, A, outs, res, gp)
+
+
+# --------------------------------------------- row orders at the boundary
+
+
+def test_library_rcm_on_generated_numbering(gp, grids):
+    """The 2,000-bus grid in the generator's numbering (bandwidth about
+    2,000) with the library ordering the rows itself (its reverse
+    Cuthill-McKee pass and its own ILU(0)): every outage against the oracle,
+    which never sees a row order."""
+    g = grids["grid2k"]
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=4, perm="rcm")
+    assert sorted(ctx.perm.tolist()) == list(range(1, g.n))
+    outs = np.arange(g.m)
+    res = _run(gp, ctx, g, outs)
+    _check_all(g, A, outs, res, gp)
+
+
+def test_shuffled_bus_numbering(gp, grids):
+    """The 200-bus grid with buses 1..n-1 relabelled at random and the
+    branch table shuffled (seeded): the library's row order, its bridge flags
+    by branch id against brute force, and every outage against the oracle on
+    the same shuffled grid; the base state against the unshuffled one."""
+    g0 = grids["grid200"]
+    rng = np.random.default_rng(19)
+    lab = np.r_[0, 1 + rng.permutation(g0.n - 1)]  # new label of each bus
+    q = rng.permutation(g0.m)                      # new branch order
+    P = np.zeros(g0.n)
+    P[lab] = g0.P
+    g = gridgen.Grid("grid200:shuffled", g0.n, lab[g0.br_from[q]].astype(np.int32),
+                     lab[g0.br_to[q]].astype(np.int32), g0.x[q].copy(), P)
+    thb, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=16, perm="rcm")
+    np.testing.assert_array_equal(ctx.bridge_flags(), [oracle.is_bridge(g, c) for c in range(g.m)])
+    np.testing.assert_allclose(ctx.base()[1], thb, rtol=1e-12, atol=1e-13)
+    thb0, _ = oracle.base_case(g0)
+    np.testing.assert_allclose(thb[lab], thb0, rtol=1e-12, atol=1e-13)
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res)
+
+
+def test_wide_row_order_is_refused_with_its_remedy(gp, grids):
+    """Rows in the generator's numbering (no row order, no reorder) have a
+    bandwidth of about 2,000 on the 2k grid, beyond a wavefront's LDS
+    window: setup refuses with a message that names the remedy."""
+    g = grids["grid2k"]
+    with pytest.raises(gp.GpcgError) as e:
+        _ctx(gp, g, block=4, perm=None)
+    assert e.value.code == -6 and "reorder" in str(e.value)
 
 
 # --------------------------------------------------------- B'' context
@@ -345,7 +413,7 @@ def test_solve_rhs_grid200(gp, grids, kind):
     g = grids["grid200"]
     shunt = np.random.default_rng(3).uniform(0, 0.05, g.n) if kind == 1 else None
     _, A = oracle.base_case(g, shunt=shunt)
-    L, U = oracle.ilu0(A)
+    gr, _, Ar, L, U, old = _oracle_rows(g, shunt=shunt)
     ctx = _ctx(gp, g, block=16, kind=kind, shunt=shunt)
     outs = np.arange(-1, g.m)
     rng = np.random.default_rng(21 + kind)
@@ -366,9 +434,9 @@ def test_solve_rhs_grid200(gp, grids, kind):
         assert st[s] == (gp.CONVERGED_ISLANDED if d["island"].any() else 0), (c, st[s])
         assert rs[s] <= RESID_TOL, (c, rs[s])
         if s % 7 == 0:
-            mask = ~d["island"][1:]
-            Ac = oracle.outage_matrix(g, A, int(c))
-            _, k, _, _ = oracle.pcg_textbook(Ac, np.where(mask, b[1:], 0.0), L, U, mask=mask, tol=1e-12)
+            mask = ~d["island"][old][1:]
+            Ac = oracle.outage_matrix(gr, Ar, int(c))
+            _, k, _, _ = oracle.pcg_textbook(Ac, np.where(mask, b[old][1:], 0.0), L, U, mask=mask, tol=1e-12)
             assert _iters_close(it[s], k), (c, it[s], k)
 
 
@@ -545,7 +613,7 @@ def test_fdpf_grid200_all_outages(gp, grids):
     from oracle import fdpf
 
     g = grids["grid200"]
-    P, Q, bsh = _fdpf_case(g, 0.02)
+    P, Q, bsh = _fdpf_case(g, 0.01)
     th_b, V_b = fdpf.base_state(g, P, Q, bsh)
     base = _fdpf_run(gp, g, P, Q, bsh, [-1], np.zeros(g.n), np.ones(g.n))
     assert np.abs(base["theta"][0] - th_b).max() <= 1e-10 and np.abs(base["V"][0] - V_b).max() <= 1e-10
@@ -610,15 +678,15 @@ def test_zero_start_grid200(gp, grids):
     textbook PCG from x0 = 0 on the re-dispatched right-hand side."""
     g = grids["grid200"]
     _, A = oracle.base_case(g)
-    L, U = oracle.ilu0(A)
-    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=16, zero_start=True)
+    gr, _, Ar, L, U, old = _oracle_rows(g)
+    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=16, zero_start=True, perm=gridgen.rcm_perm(g))
     outs = list(range(g.m))
     res = _run(gp, ctx, g, outs)
     _check_against_direct(g, A, outs, res)
     for c in outs[::7]:
-        d = oracle.scenario(g, c, A)
+        d = oracle.scenario(gr, c, Ar)
         mask = ~d["island"][1:]
-        Ac = oracle.outage_matrix(g, A, c)
+        Ac = oracle.outage_matrix(gr, Ar, c)
         _, k, _, _ = oracle.pcg_textbook(Ac, np.where(mask, d["Pp"][1:], 0.0), L, U, mask=mask, tol=1e-12)
         assert _iters_close(res["iters"][c], k), (c, res["iters"][c], k)
 
@@ -646,11 +714,11 @@ def test_overload_screening_grid2k(gp, grids):
 # ------------------------------------------------ multi-grid batches
 
 
-def _batch_inputs(gp, names, grids, block, oracle_matrix=False):
+def _batch_inputs(gp, names, grids, block):
     ctxs, outs, rhs = [], [], []
     for n in names:
         g = grids[n] if not n.startswith("hand:") else gridgen.hand_grid(n[5:])
-        ctxs.append(_ctx(gp, g, block=block, A=oracle.base_case(g)[1] if oracle_matrix else None))
+        ctxs.append(_ctx(gp, g, block=block))
         outs.append(torch.arange(g.m, dtype=torch.int32, device="cuda"))
         rhs.append(torch.tensor(g.P, device="cuda"))
     return ctxs, outs, rhs

@@ -14,6 +14,7 @@ def test_deterministic_and_sized(grids, key):
     assert g.n == spec.n and g.m == spec.m
     assert gridgen.make_grid(key).digest() == g.digest()
     # branches sorted, from < to, no duplicates (no parallel branches)
+    assert spec.order == "generated"
     assert np.all(g.br_from < g.br_to)
     pairs = g.br_from.astype(np.int64) * g.n + g.br_to
     assert np.all(np.diff(pairs) > 0)
@@ -40,11 +41,26 @@ def test_bridge_share_like_the_paper(grids):
     assert 0.25 < share < 0.55
 
 
+def _bandwidth(g):
+    keep = (g.br_from > 0) & (g.br_to > 0)
+    return int(np.max(np.abs(g.br_from[keep].astype(int) - g.br_to[keep].astype(int))))
+
+
 def test_rcm_numbering_is_banded(grids):
+    """The generated numbering is not banded; the RCM row order of the same
+    grid is, and relabelling by it keeps the grid (same branch list up to
+    the relabelling, same injections per bus)."""
     g = grids["grid2k"]
-    keep = (g.br_from > 0)
-    bw = np.max(np.abs(g.br_from[keep].astype(int) - g.br_to[keep].astype(int)))
-    assert bw < 60
+    assert _bandwidth(g) > 500
+    perm = gridgen.rcm_perm(g)
+    assert sorted(perm.tolist()) == list(range(1, g.n))
+    r = gridgen.renumber(g, perm)
+    assert _bandwidth(r) < 60
+    new = np.zeros(g.n, int)
+    new[perm] = np.arange(1, g.n)
+    np.testing.assert_array_equal(r.br_from, new[g.br_from])
+    np.testing.assert_array_equal(r.P[new], g.P)
+    assert _bandwidth(gridgen.make_grid("grid2k", order="rcm")) < 60
 
 
 def test_hand_grids_build():

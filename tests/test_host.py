@@ -89,6 +89,34 @@ def test_assembly_entries_are_correctly_rounded_sums():
     assert float(Fraction(1) + 2 * Fraction(1, 2 ** 53)) == 1.0 + 2.0 ** -52
 
 
+@pytest.mark.parametrize("key", ["grid200", "grid2k", "grid10k"])
+def test_rcm_row_order(grids, key):
+    """gpcg_rcm: a permutation of the non-slack buses, deterministic, whose
+    rows are banded (the generated numbering is not); gpcg_assemble with it
+    equals P A P^T of the bus-order assembly bit for bit."""
+    g = grids[key]
+    perm = gp.rcm(g.n, g.br_from, g.br_to)
+    assert sorted(perm.tolist()) == list(range(1, g.n))
+    np.testing.assert_array_equal(perm, gp.rcm(g.n, g.br_from, g.br_to))
+    Ap = gp.assemble(g.n, g.br_from, g.br_to, g.x, perm=perm).to_scipy()
+    coo = Ap.tocoo()
+    assert np.abs(coo.row - coo.col).max() <= 80
+    A = gp.assemble(g.n, g.br_from, g.br_to, g.x).to_scipy()
+    rows = perm - 1
+    np.testing.assert_array_equal(Ap.toarray() if g.n <= 2000 else Ap[:50].toarray(),
+                                  A[rows][:, rows].toarray() if g.n <= 2000 else A[rows[:50]][:, rows].toarray())
+
+
+def test_rcm_on_a_disconnected_reduced_graph():
+    """Without the slack the reduced graph may fall apart (slack_leaf: the
+    slack's only branch; two_rings: pieces joined through the slack);
+    every piece is ordered."""
+    for name in gridgen.HAND_GRIDS:
+        g = gridgen.hand_grid(name)
+        perm = gp.rcm(g.n, g.br_from, g.br_to)
+        assert sorted(perm.tolist()) == list(range(1, g.n)), name
+
+
 @pytest.mark.parametrize("key", ["grid200", "grid2k"])
 def test_ilu0_matches_oracle(grids, key):
     g = grids[key]
