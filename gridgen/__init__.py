@@ -19,19 +19,23 @@ order):
    (length, i, j), until ``m`` branches exist (no parallel branches);
 3. slack: the highest-degree bus of the largest 2-edge-connected component
    (ties go to the bus nearest the centre), relabelled to index 0; the other
-   buses keep their generation order as 1..n-1 (``order="generated"``, the
-   default: the numbering of the points, unrelated to the graph), or are
-   numbered in reverse Cuthill-McKee order of the graph with the slack
-   removed (``order="rcm"``).  A banded row order is a solver's concern:
-   ``rcm_perm`` gives the reverse Cuthill-McKee row order of a grid for a
-   consumer that wants one, and ``renumber`` relabels a grid by it;
-4. branches sorted by (min endpoint, max endpoint); ``from`` is the smaller;
+   buses are numbered 1..n-1 in reverse Cuthill-McKee order of the graph
+   with the slack removed, the frame in which steps 4-7 draw;
+4. branches sorted by (min endpoint, max endpoint) in that frame; ``from``
+   is the smaller;
 5. reactances ``x ~ U(x_lo, 0.3)``; optionally a seeded 5 % of branches become
    transformers with ``x ~ U(0.05, 0.2)``;
 6. active injections ``P ~ N(0, 0.5)`` (standard deviation), slack entry set so
    that the injections sum to zero;
 7. optionally reactive injections ``Q ~ N(0, 0.2)`` and shunts
-   ``b_sh ~ U(0, 0.05)``.
+   ``b_sh ~ U(0, 0.05)``;
+8. the buses are then relabelled in generation order (slack 0, the others
+   in the order of their points; ``order="generated"``, the default), a
+   numbering unrelated to the graph, with the branch ids and orientations
+   kept; ``order="rcm"`` keeps the frame of step 3.  Both describe the same
+   physical grid.  A banded row order is a solver's concern: ``rcm_perm``
+   gives SciPy's reverse Cuthill-McKee row order of a grid for a consumer
+   that wants one, and ``renumber`` relabels a grid by it.
 """
 from __future__ import annotations
 
@@ -192,15 +196,13 @@ def make_grid(spec: GridSpec | str, order: Optional[str] = None) -> Grid:
     order = np.lexsort((dc, -deg[cands]))
     slack = int(cands[order[0]])
 
-    # relabel: slack -> 0, the others in RCM order (or generation order)
+    # relabel: slack -> 0, the others in RCM order; the draws below are made
+    # in this frame, so both numberings describe the same physical grid
     new = np.empty(n, np.int64)
     rest = np.array([i for i in range(n) if i != slack], dtype=np.int64)
-    if spec.order == "rcm":
-        rest = rest[_rcm_order(n, edges, slack, rest)]
-    elif spec.order != "generated":
-        raise ValueError(f"unknown order {spec.order!r}")
+    rest_rcm = rest[_rcm_order(n, edges, slack, rest)]
     new[slack] = 0
-    new[rest] = np.arange(1, n)
+    new[rest_rcm] = np.arange(1, n)
     e = new[edges]
     e = np.sort(e, axis=1)
     e = e[np.lexsort((e[:, 1], e[:, 0]))]
@@ -218,6 +220,26 @@ def make_grid(spec: GridSpec | str, order: Optional[str] = None) -> Grid:
     if spec.reactive:
         Q = rng.normal(0.0, 0.2, n)
         bsh = rng.uniform(0.0, 0.05, n)
+    if spec.order == "generated":
+        # the same grid, buses relabelled in generation order (slack 0);
+        # branches keep their ids and orientation
+        gen = np.empty(n, np.int64)
+        gen[slack] = 0
+        gen[rest] = np.arange(1, n)
+        r2g = np.empty(n, np.int64)
+        r2g[new] = gen
+        e = r2g[e]
+
+        def bus(a):
+            if a is None:
+                return None
+            out = np.empty_like(a)
+            out[r2g] = a
+            return out
+
+        P, Q, bsh, pts_new = bus(P), bus(Q), bus(bsh), bus(pts_new)
+    elif spec.order != "rcm":
+        raise ValueError(f"unknown order {spec.order!r}")
     return Grid(spec.name, n, e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), x, P, Q, bsh, pts_new, spec.seed)
 
 

@@ -198,9 +198,12 @@ def test_determinism(gp, grids):
 
 
 def test_spmm_against_numpy(gp, grids):
+    """The stand-alone product in the context's row order (row r holds bus
+    perm[r]): 128 seeded columns against the oracle's explicit A_c."""
     g = grids["grid2k"]
     _, A = oracle.base_case(g)
     ctx = _ctx(gp, g, block=64)
+    rows = ctx.perm.astype(np.int64) - 1  # reduced index (bus - 1) of each row
     nr, S = g.n - 1, 64
     rng = np.random.default_rng(0)
     outs = rng.integers(-1, g.m, 128).astype(np.int32)
@@ -208,7 +211,7 @@ def test_spmm_against_numpy(gp, grids):
     # zero islanded entries as the solver keeps them
     masks = [~oracle.island_of(g, int(c))[1:] for c in outs]
     P = P * np.array(masks)
-    tiles = P.reshape(2, S, nr).transpose(0, 2, 1).copy()
+    tiles = P[:, rows].reshape(2, S, nr).transpose(0, 2, 1).copy()
     p = torch.tensor(tiles, device="cuda")
     q = torch.empty_like(p)
     pq = torch.empty(128, dtype=torch.float64, device="cuda")
@@ -218,7 +221,7 @@ def test_spmm_against_numpy(gp, grids):
     for k, c in enumerate(outs):
         Ac = oracle.outage_matrix(g, A, int(c))
         expect = np.where(masks[k], Ac @ P[k], 0.0)
-        np.testing.assert_allclose(qh[k], expect, rtol=1e-13, atol=1e-9)
+        np.testing.assert_allclose(qh[k], expect[rows], rtol=1e-13, atol=1e-9)
         assert pq[k].item() == pytest.approx(P[k] @ expect, rel=1e-11)
 
 
@@ -374,10 +377,12 @@ def test_spmm_grid10k_full_launch_sampled(gp, grids, S):
     """The product as the benchmark times it (block 16; block 32 takes
     another chunk height): every outage column of the 10,000-bus grid in one
     launch, p ~ N(0, 1); 64 seeded columns checked against the oracle's
-    explicit A_c (islanded rows zero) and their p'q."""
+    explicit A_c (islanded rows zero) and their p'q, in the context's row
+    order."""
     g = grids["grid10k"]
     _, A = oracle.base_case(g)
     ctx = _ctx(gp, g, block=S)
+    rows = ctx.perm.astype(np.int64) - 1
     nr = g.n - 1
     ncols = ((g.m + S - 1) // S) * S
     outs = np.arange(ncols) % g.m
@@ -396,8 +401,10 @@ def test_spmm_grid10k_full_launch_sampled(gp, grids, S):
         qj = q[j // S, :, j % S].cpu().numpy()
         c = int(outs[j])
         keep = ~oracle.island_of(g, c)[1:]
-        expect = np.where(keep, oracle.outage_matrix(g, A, c) @ pj, 0.0)
-        np.testing.assert_allclose(qj, expect, rtol=1e-13, atol=1e-9)
+        pn = np.zeros(nr)
+        pn[rows] = pj
+        expect = np.where(keep, oracle.outage_matrix(g, A, c) @ pn, 0.0)
+        np.testing.assert_allclose(qj, expect[rows], rtol=1e-13, atol=1e-9)
         assert pqh[j] == pytest.approx(float(pj @ expect), rel=1e-11)
 
 
