@@ -388,6 +388,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--dump-iters", default="", help="save per-outage iterations, status and queue order (.npz)")
     ap.add_argument("--spmm-workload", default="grid10k", help="grid of the stand-alone product measurement")
     ap.add_argument("--no-spmm", action="store_true")
     ap.add_argument("--spmm-block", type=int, default=16)
@@ -507,6 +508,8 @@ def main():
     resid = out["resid"].cpu().numpy()
     S = info["block"]
     waves, wave_iters = ctx.sweeps()  # persistent wavefronts and their iterations, last solve
+    if args.dump_iters:
+        np.savez(args.dump_iters, iters=iters, status=status, order=ctx.order(m), perm=ctx.perm)
     algo_bytes = own_work_bytes(info, iters, wave_iters, m)
     achieved = algo_bytes / (pcg_ms * 1e-3) / 1e9
     idle_overhead = float(S * wave_iters) / max(1, int(iters.sum()))

@@ -254,8 +254,12 @@ int gpcg_get_perm(gpcg_t h, int32_t *perm);
  * The scenarios are handed out by an atomic queue to persistent wavefronts
  * (as many as fit the device at once, at most one per S scenarios), each
  * with S scenario columns; a column that stops writes its results and takes
- * the next scenario, heaviest expected work first.  Workspace (4 (n_r + 1)
- * S doubles per wavefront) is owned by the context and grows on demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
+ * the next scenario, heaviest expected work first: an outage this context
+ * has solved before is ranked by the iterations it took then, others first
+ * (the context keeps one iteration record per outage id and start mode).
+ * The order changes no result: every scenario's arithmetic is the same in
+ * any column.  Workspace (4 (n_r + 1) S doubles per wavefront) is owned by
+ * the context and grows on demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
  * max_iter < 1, or flows requested from a B'' context.  Outage ids are read
  * on the device only: an id outside [-1, m) gives that scenario status
  * GPCG_BAD_OUTAGE and zero outputs, the other scenarios are unaffected.
@@ -465,7 +469,8 @@ int gpcg_spmm(gpcg_t h, int32_t ncols, const int32_t *outages, const double *p, 
 
 /*
  * Queue order of the last batched solve: order[j] is the scenario the queue
- * handed out j-th.  Scenarios are ranked by expected work (islanding
+ * handed out j-th.  Scenarios are ranked by expected work (the iterations
+ * the outage took in this context's previous solve; without one, islanding
  * outages, then the base-case flow of the outaged branch) and handed out
  * from the heaviest, so that the last ones to finish are short.  order:
  * host int32[n_out] (n_out of that call).  Synchronises the context's

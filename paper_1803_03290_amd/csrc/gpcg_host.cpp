@@ -626,6 +626,7 @@ struct gpcg_context {
     DevBuf<double> br_x, br_b, theta_b, rho_b, scal;
     DevBuf<double> ws, gfac, partial;
     DevBuf<int32_t> queue;               // the PCG launch's queue counter
+    DevBuf<int32_t> hist_base, hist_cols;  // iterations of each outage (index c + 1) in the last solve of each mode
     DevBuf<unsigned long long> sweeps;   // iterations summed over the waves of the last launch
     int last_waves = 0;                  // waves of the last PCG launch
     int max_waves[7] = {0, 0, 0, 0, 0, 0, 0};  // wavefronts that fit the device at once, per log2(block)
@@ -870,11 +871,12 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     p.rhs_ld = rhs_ld;
     p.zero_start = (!rhs_cols && h->zero_start) ? 1 : 0;
     p.add_base = (!rhs_cols && !h->zero_start) ? 1 : 0;
+    int32_t *hist = rhs_cols ? h->hist_cols.p : h->hist_base.p;
     if (needs_order(S_, n_out)) {
         // the queue hands out the scenarios of most expected work first
         hip_check(gpcg::launch_order(n_out, outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
-                                     h->isl_hi.p, h->theta_b.p, w.keys, w.keys_sorted, w.iota, w.order, w.pos, w.temp,
-                                     w.temp_bytes, h->stream),
+                                     h->isl_hi.p, h->theta_b.p, hist, w.keys, w.keys_sorted, w.iota, w.order, w.pos,
+                                     w.temp, w.temp_bytes, h->stream),
                   "scenario ordering");
         p.order = w.order;
     }
@@ -884,6 +886,8 @@ void run_solve(gpcg_context *h, int S_, int n_out, const int32_t *outages, const
     h->last_waves = w.n_waves;
     if (h->timing) hip_check(hipEventRecord(h->ev0, h->stream), "event");
     hip_check(gpcg::launch_pcg(p, S_, w.n_waves, D.ring_max(), h->stream), "pcg launch");
+    if (needs_order(S_, n_out))
+        hip_check(gpcg::launch_record_iters(n_out, outages, h->m, iters_out, hist, h->stream), "iteration records");
     if (h->timing) {
         hip_check(hipEventRecord(h->ev1, h->stream), "event");
         h->timed = true;
@@ -1153,8 +1157,8 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
             const size_t tb = gpcg::sort_temp_bytes(n);
             temp.alloc(std::max<size_t>(tb, 1));
             hip_check(gpcg::launch_order(n, G->outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
-                                         h->isl_hi.p, h->theta_b.p, keys.p, keys_sorted.p, iota.p, G->order.p,
-                                         G->pos.p, temp.p, tb, b->stream),
+                                         h->isl_hi.p, h->theta_b.p, h->hist_base.p, keys.p, keys_sorted.p, iota.p,
+                                         G->order.p, G->pos.p, temp.p, tb, b->stream),
                       "scenario ordering");
             hip_check(hipStreamSynchronize(b->stream), "ordering");
             p.order = G->order.p;
@@ -1520,6 +1524,11 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->rho_b.alloc(nr);
         h->queue.alloc(1);
         h->sweeps.alloc(1);
+        {  // no iteration records yet
+            const std::vector<int32_t> none(m + 1, -1);
+            h->hist_base.upload(none.data(), m + 1, st);
+            h->hist_cols.upload(none.data(), m + 1, st);
+        }
         hip_check(hipStreamSynchronize(st), "setup upload");
         h->schedule_for(S);
         if (theta_base) {

@@ -258,15 +258,20 @@ hipError_t launch_weighted_rows(int n_rows, int n_cols, const double *a, int lda
 constexpr size_t kStaticScratchBytes = GPCG_NOALLOC_SCRATCH_BYTES;
 hipError_t static_scratch(void **ptr);
 
-// Order scenarios by expected PCG work so that a tile's columns stop at
-// about the same iteration: non-islanding outages first, then islanding
-// ones, each by the base-case flow of the outaged branch.  Writes order[]
-// (scenario per tile position) and pos[] (its inverse).  temp / temp_bytes:
-// scratch from sort_temp_bytes().
+// Rank scenarios by expected PCG work, ascending (the queue takes them from
+// the heavy end): by the iterations each outage took in this context's
+// previous solve (hist, indexed c + 1; -1 = none; NULL: no records), and
+// outages without a record first, islanding ones before the others, each by
+// the base-case flow of the outaged branch.  Writes order[] (scenario of each
+// rank) and pos[] (its inverse).  temp / temp_bytes: scratch from
+// sort_temp_bytes().
 size_t sort_temp_bytes(int n);
 hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
                         const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi, const double *theta_b,
-                        uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order, int32_t *pos, void *temp,
-                        size_t temp_bytes, hipStream_t st);
+                        const int32_t *hist, uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order,
+                        int32_t *pos, void *temp, size_t temp_bytes, hipStream_t st);
+// hist[outages[s] + 1] = iters[s] for the valid outages
+hipError_t launch_record_iters(int n, const int32_t *outages, int m, const int32_t *iters, int32_t *hist,
+                               hipStream_t st);
 
 }  // namespace gpcg

@@ -650,22 +650,40 @@ __global__ void weighted_rows_kernel(int n_rows, int n_cols, const double *a, in
     out[j] = acc;
 }
 
-// sort key of a scenario: islanding flag, then the base flow on the branch
+// Sort key of a scenario (the queue hands out the largest keys first).  An
+// outage solved before by this context is ranked by the iterations it took
+// then (hist[c + 1]); one without such a record ranks above all of those,
+// and among themselves such outages go islanding first, then by the base
+// flow on the outaged branch (the start residual of a non-islanding outage
+// is that flow across the branch).
 __global__ void order_keys_kernel(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
                                   const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi,
-                                  const double *theta_b, uint32_t *keys, int32_t *iota) {
+                                  const double *theta_b, const int32_t *hist, uint32_t *keys, int32_t *iota) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int c = outages[j];
     uint32_t key = 0;
     if (c < -1 || c >= m) {
-        key = 0xffffffffu;
+        key = 0u;  // nothing to solve: last
+    } else if (hist && hist[c + 1] >= 0) {
+        key = (uint32_t)min(hist[c + 1], (1 << 20) - 1) << 10;
     } else if (c >= 0) {
         const float f = (float)fabs(br_b[c] * (theta_b[br_from[c]] - theta_b[br_to[c]]));
-        key = (__float_as_uint(f) >> 1) | (isl_hi[c] > isl_lo[c] ? 0x80000000u : 0u);
+        key = 0x80000000u | (isl_hi[c] > isl_lo[c] ? 0x40000000u : 0u) | (__float_as_uint(f) >> 2);
+    } else {
+        key = 0x80000000u;
     }
     keys[j] = key;
     iota[j] = j;
+}
+
+// hist[c + 1] = the iterations scenario s took (its outage c), for the
+// next solve's ranking
+__global__ void record_iters_kernel(int n, const int32_t *outages, int m, const int32_t *iters, int32_t *hist) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int c = outages[j];
+    if (c >= -1 && c < m) hist[c + 1] = iters[j];
 }
 
 __global__ void order_inverse_kernel(int n, const int32_t *order, int32_t *pos) {
@@ -708,14 +726,21 @@ size_t sort_temp_bytes(int n) {
 
 hipError_t launch_order(int n, const int32_t *outages, int m, const int32_t *br_from, const int32_t *br_to,
                         const double *br_b, const int32_t *isl_lo, const int32_t *isl_hi, const double *theta_b,
-                        uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order, int32_t *pos, void *temp,
-                        size_t temp_bytes, hipStream_t st) {
+                        const int32_t *hist, uint32_t *keys, uint32_t *keys_sorted, int32_t *iota, int32_t *order,
+                        int32_t *pos, void *temp, size_t temp_bytes, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(order_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, outages, m, br_from, br_to, br_b,
-                       isl_lo, isl_hi, theta_b, keys, iota);
+                       isl_lo, isl_hi, theta_b, hist, keys, iota);
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_sorted, iota, order, n, 0, 32, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(order_inverse_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, order, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_iters(int n, const int32_t *outages, int m, const int32_t *iters, int32_t *hist,
+                               hipStream_t st) {
+    if (n <= 0 || !hist) return hipSuccess;
+    hipLaunchKernelGGL(record_iters_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, outages, m, iters, hist);
     return hipGetLastError();
 }
 
