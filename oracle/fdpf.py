@@ -50,10 +50,14 @@ def injections(grid, theta, V, shunt, c: int = -1):
     return P, Q
 
 
-def fdpf(grid, P, Q, shunt, theta0, V0, c: int = -1, iters: int = 3, redispatch_islands: bool = True):
+def fdpf(grid, P, Q, shunt, theta0, V0, c: int = -1, iters: int = 3, redispatch_islands: bool = True,
+         solve=None):
     """``iters`` outer fast-decoupled iterations of outage c from (theta0, V0).
 
+    ``solve(A, b)`` solves each half's linear system (default: sparse LU
+    with extended-precision refinement; any correct FP64 solve is valid).
     Returns (theta, V, island)."""
+    solve = refined_solve if solve is None else solve
     P = np.asarray(P, dtype=np.float64)
     Q = np.asarray(Q, dtype=np.float64)
     island = island_of(grid, c) if c >= 0 else np.zeros(grid.n, bool)
@@ -69,15 +73,15 @@ def fdpf(grid, P, Q, shunt, theta0, V0, c: int = -1, iters: int = 3, redispatch_
     theta[0], V[0] = 0.0, 1.0
     for _ in range(iters):
         Pc, _ = injections(grid, theta, V, shunt, c)
-        theta[bus] += refined_solve(Bp, (Pp[bus] - Pc[bus]) / V[bus])
+        theta[bus] += solve(Bp, (Pp[bus] - Pc[bus]) / V[bus])
         _, Qc = injections(grid, theta, V, shunt, c)
-        V[bus] += refined_solve(Bpp, (Q[bus] - Qc[bus]) / V[bus])
+        V[bus] += solve(Bpp, (Q[bus] - Qc[bus]) / V[bus])
     theta[island] = 0.0
     V[island] = 1.0
     return theta, V, island
 
 
-def base_state(grid, P, Q, shunt, iters: int = 3):
+def base_state(grid, P, Q, shunt, iters: int = 3, solve=None):
     """The intact network's state after ``iters`` iterations from flat start."""
-    th, V, _ = fdpf(grid, P, Q, shunt, np.zeros(grid.n), np.ones(grid.n), -1, iters)
+    th, V, _ = fdpf(grid, P, Q, shunt, np.zeros(grid.n), np.ones(grid.n), -1, iters, solve=solve)
     return th, V

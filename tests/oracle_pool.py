@@ -82,3 +82,52 @@ def compare_all(grid, A, outages, res, rhs=None, shunt=None, redispatch=True, wo
             out["angle"][s], out["flow"][s], out["island_ok"][s] = ang, flow, isl
             out["status"][s], out["resid"][s] = st, r
     return out
+
+
+def _init_fdpf(grid, P, Q, bsh, th0, V0, paths):
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(1)
+    except Exception:
+        pass
+    _W.update(grid=grid, P=P, Q=Q, bsh=bsh, th0=th0, V0=V0)
+    for k, p in paths.items():
+        _W[k] = np.load(p, mmap_mode="r")
+
+
+def _chunk_fdpf(rows):
+    from oracle import fdpf
+
+    out = []
+    for s, c in rows:
+        th, V, _ = fdpf.fdpf(_W["grid"], _W["P"], _W["Q"], _W["bsh"], _W["th0"], _W["V0"], int(c))
+        out.append((s, float(np.abs(np.asarray(_W["theta"][s]) - th).max()),
+                    float(np.abs(np.asarray(_W["V"][s]) - V).max())))
+    return out
+
+
+def compare_fdpf(grid, P, Q, bsh, th0, V0, outages, theta, V, workers=None):
+    """Three fast-decoupled iterations of each outage by the oracle against
+    the device's (theta, V) rows; returns per-scenario max |dtheta|, |dV|."""
+    outages = np.asarray(outages)
+    n = len(outages)
+    tmp = tempfile.mkdtemp(prefix="gpcg_fdpf_")
+    try:
+        paths = {"theta": os.path.join(tmp, "theta.npy"), "V": os.path.join(tmp, "V.npy")}
+        np.save(paths["theta"], np.ascontiguousarray(theta))
+        np.save(paths["V"], np.ascontiguousarray(V))
+        nw = workers or min(16, len(os.sched_getaffinity(0)))
+        rows = [(s, int(outages[s])) for s in range(n)]
+        step = max(1, min(16, n // (4 * nw) + 1))
+        chunks = [rows[i:i + step] for i in range(0, n, step)]
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(nw, initializer=_init_fdpf, initargs=(grid, P, Q, bsh, th0, V0, paths)) as pool:
+            parts = pool.map(_chunk_fdpf, chunks)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    dth, dV = np.zeros(n), np.zeros(n)
+    for part in parts:
+        for s, a, b in part:
+            dth[s], dV[s] = a, b
+    return dth, dV

@@ -159,6 +159,71 @@ def test_grid200_plain_matches_batched(gp, grids):
     np.testing.assert_array_equal(a["status"], b["status"])
 
 
+# ------------------------------------------- pins through the device path
+
+
+def _lu_nopivot(A):
+    """Exact LU without pivoting by dense Gaussian elimination: (L strictly
+    lower, U upper with the diagonal) as CSR."""
+    import scipy.sparse as sp
+
+    a = A.toarray().astype(float)
+    n = a.shape[0]
+    for k in range(n):
+        a[k + 1:, k] /= a[k, k]
+        a[k + 1:, k + 1:] -= np.outer(a[k + 1:, k], a[k, k + 1:])
+    L = sp.csr_matrix(np.tril(a, -1))
+    U = sp.csr_matrix(np.triu(a))
+    L.sort_indices()
+    U.sort_indices()
+    return L, U
+
+
+def _csr(gp, M):
+    M = M.tocsr()
+    M.sort_indices()
+    return gp.binding.Csr(M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def test_exact_factors_converge_in_one_step(gp, grids):
+    """Given the exact LU of the base matrix as its "ILU" factors, the
+    correction-form start from the base state makes the first search
+    direction parallel to the Sherman-Morrison correction, so every
+    non-islanding outage converges in one step in exact arithmetic (two at
+    most in FP64), with angles equal to the direct solve."""
+    g = grids["grid200"]
+    perm = gridgen.rcm_perm(g)
+    gr = gridgen.renumber(g, perm)
+    _, Ar = oracle.base_case(gr)
+    L, U = _lu_nopivot(Ar)
+    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=16, perm=perm, A=_csr(gp, Ar), L=_csr(gp, L),
+                     U=_csr(gp, U))
+    _, A = oracle.base_case(g)
+    outs = [c for c in range(g.m) if not oracle.is_bridge(g, c)]
+    res = _run(gp, ctx, g, outs, tol=1e-12)
+    assert res["iters"].max() <= 2, res["iters"].max()
+    _check_against_direct(g, A, outs, res)
+
+
+@pytest.mark.parametrize("block", [16, 1])
+def test_breakdown_status_on_a_negative_definite_operator(gp, grids, block):
+    """A sign-flipped operator (A = -B', factors of +B', base state 0): the
+    first p'Ap is negative, so every scenario stops with BREAKDOWN after no
+    step, in the batched and the plain form, and the results stay at the
+    start (zero angles)."""
+    g = grids["grid200"]
+    perm = gridgen.rcm_perm(g)
+    Ap = gp.assemble(g.n, g.br_from, g.br_to, g.x, perm=perm)
+    L, U = gp.ilu0(Ap)
+    An = gp.binding.Csr(Ap.rowptr, Ap.col, -Ap.val)
+    ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, None, theta_base=np.zeros(g.n), block=block, perm=perm, A=An,
+                     L=L, U=U)
+    outs = [c for c in range(40) if not oracle.is_bridge(g, c)]
+    res = _run(gp, ctx, g, outs, plain=block == 1)
+    assert np.all(res["status"] == gp.BREAKDOWN), res["status"]
+    assert np.all(res["iters"] == 0) and np.all(res["x"] == 0.0)
+
+
 # ------------------------------------------------------- edge cases
 
 
@@ -547,25 +612,36 @@ def test_overload_autograd_function(gp, grids):
     assert np.abs(x.grad.cpu().numpy() - gx).max() <= 1e-6 * np.abs(gx).max()
 
 
-def test_overload_gradients_grid10k_sampled_fd(gp, grids):
+def test_overload_gradients_grid10k(gp, grids, capsys):
     """The differentiation workload at full size: every outage of the
-    10,000-bus grid in one call at block 16; for 3 seeded outages, 9 seeded
-    entries of dL/dP and 8 of dL/dx (51 in all) against central differences
-    of the oracle's refined direct loss, to 1e-6 of the gradient's largest
-    entry.  The step is h = 1e-6 first.  Angles reach thousands of radians on
-    this grid, so even the refined loss carries rounding noise of a few 1e-9,
-    which a step of 1e-6 amplifies past the bar on some entries; those are
-    checked with the Richardson extrapolation (4 D(h/2) - D(h)) / 3 of
-    central differences at h = 1e-4, which removes the h^2 term while the
-    noise stays about 1e-4 times smaller than at h = 1e-6."""
+    10,000-bus grid in one call (block 8).  Statuses of both solves of every
+    outage against the brute-force islands.  For 6 seeded outages (3
+    islanding), the loss and the full rows dL/dP (10,000) and dL/dx (13,500)
+    against the oracle's adjoint with sparse-LU solves, to 1e-6 of each
+    row's largest entry (the target bar).  And 50 seeded entries of those
+    rows against central differences of the oracle's refined direct loss,
+    |D - G_j| <= 1e-6 max(|G_j|, 1e-3 ||G||_inf), first at h = 1e-6; an entry
+    whose difference is swamped by the loss's rounding (angles of
+    thousands of radians) is taken again as the Richardson extrapolation
+    (4 D(h/2) - D(h)) / 3 at h = 1e-4; the number of such entries is
+    printed."""
     from oracle import adjoint
 
     g = grids["grid10k"]
     F = adjoint.flow_limits(g)
-    ctx = _ctx(gp, g, block=16)
+    ctx = _ctx(gp, g, block=8)
     outs = np.arange(g.m)
     res = _overload(gp, ctx, g, outs, F)
-    assert np.all(res["status"][g.m:] <= gp.CONVERGED_ISLANDED)
+    for c in outs:
+        isl = oracle.island_of(g, int(c))
+        nogen = oracle.redispatch(g.P, isl)[1]
+        fwd = 0 if not isl.any() else (gp.ISLANDED_NO_GEN if nogen else gp.CONVERGED_ISLANDED)
+        assert res["status"][c] == fwd, (c, res["status"][c], fwd)
+        assert res["status"][g.m + c] == (gp.CONVERGED_ISLANDED if isl.any() else gp.CONVERGED), c
+    rng = np.random.default_rng(17)
+    bridge = np.array([oracle.is_bridge(g, int(c)) for c in range(g.m)])
+    picks = np.r_[rng.choice(np.flatnonzero(~bridge), 3, replace=False),
+                  rng.choice(np.flatnonzero(bridge), 3, replace=False)]
 
     def fd(fun, v, j, h):
         vp, vm = v.copy(), v.copy()
@@ -573,21 +649,30 @@ def test_overload_gradients_grid10k_sampled_fd(gp, grids):
         vm[j] -= h
         return (fun(vp) - fun(vm)) / (2 * h)
 
-    def check(fun, v, j, grad, scale):
-        d1 = fd(fun, v, j, 1e-6)
-        if abs(d1 - grad) <= 1e-6 * scale:
-            return
-        d2 = (4.0 * fd(fun, v, j, 5e-5) - fd(fun, v, j, 1e-4)) / 3.0
-        assert abs(d2 - grad) <= 1e-6 * scale, (j, d1, d2, grad)
-
-    rng = np.random.default_rng(17)
-    for c in rng.choice(g.m, 3, replace=False):
-        gp_row, gx_row = res["grad_p"][c], res["grad_x"][c]
-        sp_, sx_ = max(np.abs(gp_row).max(), 1.0), max(np.abs(gx_row).max(), 1.0)
-        for j in rng.choice(np.arange(1, g.n), 9, replace=False):
-            check(lambda v: adjoint.scenario_loss(g, int(c), v, g.x, F), g.P, j, gp_row[j], sp_)
-        for e in rng.choice(g.m, 8, replace=False):
-            check(lambda v: adjoint.scenario_loss(g, int(c), g.P, v, F), g.x, e, gx_row[e], sx_)
+    fallback = 0
+    n_fd = 0
+    for k, c in enumerate(picks):
+        L, dP, dx = adjoint.gradients_sparse(g, int(c), g.P, g.x, F)
+        assert res["loss"][c] == pytest.approx(L, rel=1e-9), c
+        assert np.abs(res["grad_p"][c] - dP).max() <= 1e-6 * np.abs(dP).max(), c
+        assert np.abs(res["grad_x"][c] - dx).max() <= 1e-6 * np.abs(dx).max(), c
+        for name, row, v, fun in (
+                ("P", res["grad_p"][c], g.P, lambda v: adjoint.scenario_loss(g, int(c), v, g.x, F)),
+                ("x", res["grad_x"][c], g.x, lambda v: adjoint.scenario_loss(g, int(c), g.P, v, F))):
+            cand = np.arange(1, g.n) if name == "P" else np.arange(g.m)
+            for j in rng.choice(cand, 4 if k % 2 else 5, replace=False):
+                bar = 1e-6 * max(abs(row[j]), 1e-3 * np.abs(row).max())
+                n_fd += 1
+                d1 = fd(fun, v, j, 1e-6)
+                if abs(d1 - row[j]) <= bar:
+                    continue
+                fallback += 1
+                d2 = (4.0 * fd(fun, v, j, 5e-5) - fd(fun, v, j, 1e-4)) / 3.0
+                assert abs(d2 - row[j]) <= bar, (c, name, j, d1, d2, row[j])
+    assert n_fd >= 50
+    with capsys.disabled():
+        print(f"\n[overload 10k] {n_fd} entries by central differences, {fallback} needed the h = 1e-4 "
+              f"Richardson step", flush=True)
 
 
 # ------------------------------------------ fast-decoupled power flow
@@ -643,20 +728,28 @@ def test_fdpf_grid200_all_outages(gp, grids):
 def test_fdpf_grid10k_sampled(gp, grids):
     """The power-flow workload on the 10,000-bus grid: all 13,500 outages,
     three outer iterations from the base state, at 1e-4 of the workload's
-    injections and shunts (the loading where the iteration converges on this
-    grid); 10 seeded outages against the oracle."""
+    injections and shunts (at the full draws the iteration diverges and two
+    correct implementations disagree beyond any bar after three iterations,
+    see test_full_loading_three_iterations_are_not_comparable); every status
+    checked, and 500 seeded outages against the oracle (CPU worker pool):
+    |dtheta| <= 1e-8 rad, |dV| <= 1e-8."""
     from oracle import fdpf
+    from oracle_pool import compare_fdpf
 
     g = grids["grid10k"]
     P, Q, bsh = _fdpf_case(g, 1e-4)
     th_b, V_b = fdpf.base_state(g, P, Q, bsh)
     outs = np.arange(g.m)
     res = _fdpf_run(gp, g, P, Q, bsh, outs, th_b, V_b)
-    assert np.all(res["status"] != gp.NONFINITE) and np.all(res["status"] != gp.MAX_ITER)
-    for c in np.random.default_rng(23).choice(g.m, 10, replace=False):
-        th, V, _ = fdpf.fdpf(g, P, Q, bsh, th_b, V_b, int(c))
-        assert np.abs(res["theta"][c] - th).max() <= 1e-8, (c, np.abs(res["theta"][c] - th).max())
-        assert np.abs(res["V"][c] - V).max() <= 1e-8, (c, np.abs(res["V"][c] - V).max())
+    for c in outs:
+        isl = oracle.island_of(g, int(c))
+        nogen = not np.any((~isl[1:]) & (P[1:] > 0))
+        exp = 0 if not isl.any() else (gp.ISLANDED_NO_GEN if nogen else gp.CONVERGED_ISLANDED)
+        assert res["status"][c] == exp, (c, res["status"][c], exp)
+    sample = np.sort(np.random.default_rng(23).choice(g.m, 500, replace=False))
+    dth, dV = compare_fdpf(g, P, Q, bsh, th_b, V_b, sample, res["theta"][sample], res["V"][sample])
+    assert dth.max() <= 1e-8, (sample[np.argmax(dth)], dth.max())
+    assert dV.max() <= 1e-8, (sample[np.argmax(dV)], dV.max())
 
 
 # ------------------------------------------------ ablations (Jacobi, x0 = 0)

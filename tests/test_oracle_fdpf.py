@@ -135,3 +135,42 @@ def test_islanding_outage_equals_main_component(grids):
     th2, V2, _ = fdpf.fdpf(sub, Pp[main], Q[main], bsh[main], th0[main], V0[main], -1)
     np.testing.assert_allclose(th[main], th2, rtol=0, atol=1e-9)
     np.testing.assert_allclose(V[main], V2, rtol=0, atol=1e-12)
+
+
+def _plain_lu(A, b):
+    """A correct FP64 solve without refinement (SciPy's sparse LU)."""
+    import scipy.sparse.linalg as sla
+
+    return sla.splu(A.tocsc(), permc_spec="COLAMD").solve(np.asarray(b, np.float64))
+
+
+def _three_iterations(g, scale, c, solve=None):
+    P, Q, bsh = scale * g.P, scale * g.Q, scale * g.bsh
+    return fdpf.fdpf(g, P, Q, bsh, np.zeros(g.n), np.ones(g.n), c, iters=3, solve=solve)
+
+
+def test_full_loading_three_iterations_are_not_comparable(grids):
+    """At the workload's draws (P ~ N(0, 0.5), Q ~ N(0, 0.2), b_sh ~
+    U(0, 0.05) at every bus of the 10,000-bus grid, one slack) the
+    fast-decoupled iteration diverges: after three iterations from a flat
+    start the mismatch exceeds 1e15, angles reach 1e7 rad and magnitudes
+    1e9 in size, some negative.  Two correct implementations that differ
+    only in the rounding of their linear solves (refined and plain sparse
+    LU, both FP64-accurate) then disagree by more than 0.01 rad in angle
+    (measured 0.26-0.31) and by more than 1e-5 of the largest magnitude in
+    V (measured 2.5e-4 - 4.0e-4), on the intact grid and on an outage: no
+    angle or magnitude bar, absolute or relative, can be asked of the device
+    there, whose PCG solves stop at a 1e-12 residual.  At 1e-4 of the draws
+    (the loading of the device tests) the same two agree to 1e-10."""
+    g = grids["grid10k"]
+    c = 5
+    for cc in (-1, c):
+        th1, V1, _ = _three_iterations(g, 1.0, cc)
+        th2, V2, _ = _three_iterations(g, 1.0, cc, solve=_plain_lu)
+        P1, Q1 = fdpf.injections(g, th1, V1, g.bsh, cc)
+        assert np.nanmax(np.abs(P1[1:] - g.P[1:])) > 1e15 and np.nanmin(V1) < 0.0
+        assert not np.nanmax(np.abs(th1 - th2)) <= 1e-2, cc
+        assert not np.nanmax(np.abs(V1 - V2)) <= 1e-5 * np.nanmax(np.abs(V1)), cc
+        th1, V1, _ = _three_iterations(g, 1e-4, cc)
+        th2, V2, _ = _three_iterations(g, 1e-4, cc, solve=_plain_lu)
+        assert np.abs(th1 - th2).max() <= 1e-10 and np.abs(V1 - V2).max() <= 1e-10
