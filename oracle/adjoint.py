@@ -53,12 +53,36 @@ def flow_limits(grid, P=None) -> np.ndarray:
     return 1.2 * np.abs(flows(grid, th)) + 0.1
 
 
-def scenario_loss(grid, c: int, P, x, F, kappa: float = 20.0) -> float:
-    """The loss of outage c from the direct (refined) scenario solve."""
+def scenario_loss(grid, c: int, P, x, F, kappa: float = 20.0, extended: bool = False) -> float:
+    """The loss of outage c from the direct (refined) scenario solve.
+
+    With ``extended`` the main-system angles, the flows and the loss are kept
+    in ``longdouble`` (the refined solve's own precision) instead of being
+    rounded to FP64: on large grids, where angles reach thousands of
+    radians, the FP64 loss carries rounding of order 1e-13 relative, which
+    central differences of small steps would amplify."""
     g = with_reactances(grid, x)
-    d = scenario(g, int(c), rhs=np.asarray(P, dtype=np.float64))
-    z = kappa * (np.abs(d["flows"]) / F - 1.0)
-    return float(np.sum(softplus(z)))
+    P = np.asarray(P, dtype=np.float64)
+    if not extended:
+        d = scenario(g, int(c), rhs=P)
+        z = kappa * (np.abs(d["flows"]) / F - 1.0)
+        return float(np.sum(softplus(z)))
+    from .system import refined_solve
+
+    island = island_of(g, int(c))
+    Pp, _ = redispatch(P, island)
+    idx = np.flatnonzero(~island[1:])
+    Amm = outage_matrix(g, reduced(susceptance_full(g)), int(c))[idx][:, idx].tocsr()
+    th = np.zeros(g.n, dtype=np.longdouble)
+    th[idx + 1] = refined_solve(Amm, Pp[idx + 1], steps=6, extended=True)
+    ld = np.longdouble
+    f = (th[g.br_from] - th[g.br_to]) / np.asarray(g.x, dtype=ld)
+    if c >= 0:
+        f[int(c)] = 0
+    inside = island[g.br_from] & island[g.br_to]
+    f[inside] = 0
+    z = ld(kappa) * (np.abs(f) / np.asarray(F, dtype=ld) - 1)
+    return float(np.sum(np.logaddexp(ld(0), z)))
 
 
 def redispatch_jacobian(P, island) -> np.ndarray:

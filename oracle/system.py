@@ -154,22 +154,24 @@ def _residual_ld(A: sp.csr_matrix, x: np.ndarray, b: np.ndarray) -> np.ndarray:
     return np.asarray(b, dtype=np.longdouble) - Ald @ np.asarray(x, dtype=np.longdouble)
 
 
-def refined_solve(A: sp.csr_matrix, b: np.ndarray, steps: int = 4) -> np.ndarray:
+def refined_solve(A: sp.csr_matrix, b: np.ndarray, steps: int = 4, extended: bool = False) -> np.ndarray:
     """Sparse LU solve followed by iterative refinement.
 
     The residual of each refinement step is formed in extended precision
     (x86 80-bit ``longdouble``), the correction solved with the same FP64 LU
-    factors; the result is the FP64 solution to within a few ulps.
+    factors; the result is the FP64 solution to within a few ulps (with
+    ``extended``, the refined solution itself is returned in ``longdouble``,
+    several digits beyond FP64).
     """
     if A.shape[0] == 0:
-        return np.zeros(0)
+        return np.zeros(0, dtype=np.longdouble if extended else np.float64)
     lu = sla.splu(A.tocsc(), permc_spec="COLAMD")
     xl = np.asarray(lu.solve(np.asarray(b, dtype=np.float64)), dtype=np.longdouble)
     for _ in range(steps):
         r = np.asarray(b, dtype=np.longdouble) - A.astype(np.longdouble) @ xl
         d = lu.solve(np.asarray(r, dtype=np.float64))
         xl = xl + np.asarray(d, dtype=np.longdouble)
-    return np.asarray(xl, dtype=np.float64)
+    return xl if extended else np.asarray(xl, dtype=np.float64)
 
 
 def base_case(grid, rhs=None, shunt=None):
