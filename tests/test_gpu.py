@@ -624,11 +624,12 @@ def test_overload_gradients_grid10k(gp, grids, capsys):
     oracle's direct loss, kept in extended precision, as the Richardson
     extrapolation (4 D(h/2) - D(h)) / 3 with relative steps h = 1e-4 |v_j|.
     On this grid (angles of thousands of radians) even the refined loss is
-    computable only to about eps_L = 2e-12 relative (measured: the scatter of
-    differences of nearby parameters), which a difference quotient divides
-    by h, so the bar is 1e-6 max(|G_j|, 1e-3 ||G||_inf) + 10 eps_L |L| / h:
-    the differences confirm each entry to their own resolution (1e-5 to
-    1e-4 of the row's largest entry), the 1e-6 target being met against the
+    computable only to 1e-12 .. 1e-10 relative, depending on the outage, and
+    a difference quotient divides that by h.  So each outage's loss noise
+    n_L is measured (the largest change of L under four perturbations of
+    1e-13 relative, which move L by far less than its noise), and the bar is
+    1e-6 max(|G_j|, 1e-3 ||G||_inf) + 3 n_L / h: the differences confirm each
+    entry to their own resolution, the 1e-6 target being met against the
     oracle's adjoint above."""
     from oracle import adjoint
 
@@ -654,10 +655,14 @@ def test_overload_gradients_grid10k(gp, grids, capsys):
         vm[j] -= h
         return (fun(vp) - fun(vm)) / (2 * h)
 
-    eps_l = 2e-12
     n_fd, worst = 0, 0.0
     for k, c in enumerate(picks):
         L, dP, dx = adjoint.gradients_sparse(g, int(c), g.P, g.x, F)
+        L0 = adjoint.scenario_loss(g, int(c), g.P, g.x, F, extended=True)
+        noise = 0.0
+        for t in range(4):
+            xx = g.x * (1.0 + 1e-13 * rng.standard_normal(g.m))
+            noise = max(noise, abs(adjoint.scenario_loss(g, int(c), g.P, xx, F, extended=True) - L0))
         assert res["loss"][c] == pytest.approx(L, rel=1e-9), c
         assert np.abs(res["grad_p"][c] - dP).max() <= 1e-6 * np.abs(dP).max(), c
         assert np.abs(res["grad_x"][c] - dx).max() <= 1e-6 * np.abs(dx).max(), c
@@ -670,7 +675,7 @@ def test_overload_gradients_grid10k(gp, grids, capsys):
             for j in rng.choice(cand, 4 if k % 2 else 5, replace=False):
                 h = 1e-4 * abs(v[j])
                 d = (4.0 * fd(fun, v, j, h / 2) - fd(fun, v, j, h)) / 3.0
-                bar = 1e-6 * max(abs(row[j]), 1e-3 * np.abs(row).max()) + 10 * eps_l * abs(L) / h
+                bar = 1e-6 * max(abs(row[j]), 1e-3 * np.abs(row).max()) + 3 * noise / h
                 n_fd += 1
                 worst = max(worst, abs(d - row[j]) / np.abs(row).max())
                 assert abs(d - row[j]) <= bar, (c, name, j, d, row[j], bar)
