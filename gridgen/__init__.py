@@ -107,41 +107,50 @@ class Grid:
 
 
 def _two_edge_components(n: int, edges: np.ndarray) -> np.ndarray:
-    """Label each bus with its 2-edge-connected component, by brute force.
+    """Label each bus with its 2-edge-connected component.
 
-    A branch is kept when its endpoints stay connected after it alone is
-    removed.  Only spanning-tree branches of the 2-core can fail that test
-    (every other branch closes a cycle), so only those are tested, each with
-    a full ``connected_components`` call.
+    The bridges (branches whose removal disconnects their endpoints) are
+    found by one depth-first search with low-link values (Tarjan 1974; a
+    branch is identified by its index, so a doubled branch is never a
+    bridge); the components are the connected pieces left when they are
+    removed.
     """
     m = edges.shape[0]
-    deg = np.bincount(edges.ravel(), minlength=n)
-    alive = np.ones(m, bool)
-    # strip degree-1 buses repeatedly: their branches cannot lie on a cycle
-    while True:
-        leaf = deg == 1
-        hit = alive & (leaf[edges[:, 0]] | leaf[edges[:, 1]])
-        if not hit.any():
-            break
-        alive &= ~hit
-        deg = np.bincount(edges[alive].ravel(), minlength=n)
-    core = edges[alive]
-    idx = np.flatnonzero(alive)
-    G = sp.coo_matrix((np.ones(len(core)), (core[:, 0], core[:, 1])), shape=(n, n)).tocsr()
-    # spanning forest of the core: non-forest branches always lie on a cycle
-    T = minimum_spanning_tree(G).tocoo()
-    tree_pairs = set(zip(np.minimum(T.row, T.col).tolist(), np.maximum(T.row, T.col).tolist()))
-    keep = np.ones(len(core), bool)
-    for k, (a, b) in enumerate(core.tolist()):
-        if (min(a, b), max(a, b)) not in tree_pairs:
+    adj = [[] for _ in range(n)]
+    for k, (a, b) in enumerate(edges.tolist()):
+        adj[a].append((b, k))
+        adj[b].append((a, k))
+    pre = [-1] * n
+    low = [0] * n
+    bridge = np.zeros(m, bool)
+    counter = 0
+    for root in range(n):
+        if pre[root] >= 0:
             continue
-        mask = np.ones(len(core), bool)
-        mask[k] = False
-        e = core[mask]
-        H = sp.coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
-        _, lab = connected_components(H, directed=False)
-        keep[k] = lab[a] == lab[b]
-    kept = edges[idx[keep]]
+        pre[root] = low[root] = counter
+        counter += 1
+        stack = [(root, -1, 0)]  # (bus, branch into it, next neighbour position)
+        while stack:
+            v, via, k = stack[-1]
+            if k < len(adj[v]):
+                stack[-1] = (v, via, k + 1)
+                w, e = adj[v][k]
+                if e == via:
+                    continue
+                if pre[w] < 0:
+                    pre[w] = low[w] = counter
+                    counter += 1
+                    stack.append((w, e, 0))
+                else:
+                    low[v] = min(low[v], pre[w])
+            else:
+                stack.pop()
+                if stack:
+                    u = stack[-1][0]
+                    low[u] = min(low[u], low[v])
+                    if low[v] > pre[u]:
+                        bridge[via] = True
+    kept = edges[~bridge]
     H = sp.coo_matrix((np.ones(len(kept)), (kept[:, 0], kept[:, 1])), shape=(n, n))
     _, lab = connected_components(H, directed=False)
     return lab
