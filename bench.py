@@ -319,11 +319,14 @@ UNEVEN = ("uneven500", "uneven1000", "uneven2000", "uneven3000", "uneven5000", "
           "uneven20000")
 
 
-def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN):
+BATCH_SHAPES = ((4, 0), (8, 0), (16, 0), (8, 64), (8, 1024))
+
+
+def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN, shapes=BATCH_SHAPES):
     """The uneven workload: all outages of eight grids (500 to 20,000 buses)
-    in one graph-captured launch; the block is picked by the autotuner
-    (blocks 4, 8 and 16, one timed solve each).  Timed with HIP events on the
-    contexts' stream around ``reps`` graph replays."""
+    in one graph-captured launch; the tile shape (block, look-ahead window)
+    is picked by the autotuner over ``shapes``, one timed solve each.  Timed
+    with HIP events on the contexts' stream around ``reps`` graph replays."""
     import numpy as np
 
     import gridgen
@@ -343,11 +346,11 @@ def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNE
     outs = [torch.arange(g.m, dtype=torch.int32, device=dev) for g in grids]
     rhs = [torch.tensor(g.P, dtype=torch.float64, device=dev) for g in grids]
     tune_ms = {}
-    for cand in (4, 8, 16):  # the autotuner's search, one candidate per call so that progress shows
+    for cand in shapes:  # the autotuner's search, one candidate per call so that progress shows
         tune_ms.update(gp.batch_tune(ctxs, outs, rhs, (cand,), tol, max_iter))
-        progress(f"block {cand}: {tune_ms[cand]:.1f} ms per solve")
-    S = min(tune_ms, key=tune_ms.get)
-    b = gp.Batch(ctxs, outs, rhs, block=S, tol=tol, max_iter=max_iter, flows=True)
+        progress(f"block {cand[0]}, look-ahead {cand[1] or 'default'}: {tune_ms[cand]:.1f} ms per solve")
+    S, look = min(tune_ms, key=tune_ms.get)
+    b = gp.Batch(ctxs, outs, rhs, block=S, tol=tol, max_iter=max_iter, flows=True, lookahead=look)
     b.run()
     torch.cuda.synchronize()
     progress("batch built and captured")
@@ -365,8 +368,9 @@ def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNE
     b.close()
     return {"workload": f"uneven batch: {len(grids)} grids of {grids[0].n} to {grids[-1].n} buses, all {n} outages "
                         f"in one graph-captured launch, tol {tol:g}",
-            "value": n / (ms * 1e-3), "unit": "scenarios/s", "ms": ms, "block": S,
-            "tuner_ms_per_solve": tune_ms, "max_true_rel_residual": resid,
+            "value": n / (ms * 1e-3), "unit": "scenarios/s", "ms": ms, "block": S, "lookahead": look,
+            "tuner_ms_per_solve": {f"{b}/{lk}": v for (b, lk), v in tune_ms.items()},
+            "max_true_rel_residual": resid,
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
 
 

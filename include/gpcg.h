@@ -409,11 +409,14 @@ int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const do
  * Batches of grids (the uneven multi-grid workload).  A batch fixes, for
  * n_ctx contexts of different grids on one device and stream, their scenario
  * lists, right-hand sides and output buffers (arrays of n_ctx device
- * pointers, given in host arrays), one block size S for all, tol and
- * max_iter.  Its solve is the batched PCG of gpcg_solve_contingencies for
- * every grid, with the tiles of all grids in ONE launch of the tile kernel
- * (heaviest grid first, so long tiles start early), captured once in a HIP
- * graph together with each grid's base-state residual and output kernels.
+ * pointers, given in host arrays), one tile shape for all - block size S and
+ * the triangular schedules' look-ahead window (lookahead rows; 0 = each
+ * context's own) - tol and max_iter.  Its solve is the batched PCG of
+ * gpcg_solve_contingencies for every grid in ONE persistent launch: every
+ * wavefront works through the grids heaviest first, taking scenarios from
+ * each grid's queue until it is empty, so waves done with a large grid move
+ * on to the smaller ones; the launch is captured once in a HIP graph
+ * together with each grid's base-state residual and output kernels.
  *   gpcg_batch_create  builds the batch (schedules for S, its own
  *                      workspace and scenario order per grid), runs one
  *                      solve eagerly, captures the graph;
@@ -426,7 +429,8 @@ int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const do
  * solve.  Errors as for gpcg_solve_contingencies, plus GPCG_E_ARG when the
  * contexts do not share a device and a stream.
  */
-int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int32_t block, const int32_t *n_outs,
+int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int32_t block, int32_t lookahead,
+                      const int32_t *n_outs,
                       const int32_t *const *outages, const double *const *rhs, double tol, int32_t max_iter,
                       double *const *x_out, double *const *flows_out, int32_t *const *iters_out,
                       int32_t *const *status_out, double *const *resid_out);
@@ -434,15 +438,16 @@ int gpcg_batch_run(gpcg_batch_t b);
 void gpcg_batch_destroy(gpcg_batch_t b);
 
 /*
- * The block-size search of the batch autotuner: for each candidate S in
- * cand[0..n_cand), a batch of the same inputs is built and its solve timed
- * (one warm-up, then reps solves, HIP events); ms_out[k] = milliseconds per
- * solve.  Outputs go to scratch buffers.  The caller keeps the best block
- * (and may cache it per grid set).
+ * The tile-shape search of the batch autotuner: for each candidate k, block
+ * cand[k] and look-ahead window cand_look[k] (cand_look may be NULL: each
+ * context's own window), a batch of the same inputs is built and its solve
+ * timed (one warm-up, then reps solves, HIP events); ms_out[k] =
+ * milliseconds per solve.  Outputs go to scratch buffers.  The caller keeps
+ * the best shape (and may cache it per grid set).
  */
 int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, const int32_t *const *outages,
                     const double *const *rhs, double tol, int32_t max_iter, int32_t n_cand, const int32_t *cand,
-                    int32_t reps, double *ms_out);
+                    const int32_t *cand_look, int32_t reps, double *ms_out);
 
 /*
  * The same computation with the plain per-scenario PCG: one scenario at a

@@ -73,12 +73,12 @@ SIGNATURES = {
                                           _VP, _VP, _VP, _VP]),
     "gpcg_weighted_rows": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, C.c_int32, _VP, _VP]),
     "gpcg_screen_overloads": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
-    "gpcg_batch_create": (C.c_int, [C.POINTER(_VP), C.c_int32, _VP, C.c_int32, _i32p, _VP, _VP, C.c_double,
-                                    C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "gpcg_batch_create": (C.c_int, [C.POINTER(_VP), C.c_int32, _VP, C.c_int32, C.c_int32, _i32p, _VP, _VP,
+                                    C.c_double, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "gpcg_batch_run": (C.c_int, [_VP]),
     "gpcg_batch_destroy": (None, [_VP]),
     "gpcg_batch_tune": (C.c_int, [C.c_int32, _VP, _i32p, _VP, _VP, C.c_double, C.c_int32, C.c_int32, _i32p,
-                                  C.c_int32, _f64p]),
+                                  _i32p, C.c_int32, _f64p]),
     "gpcg_fdpf": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP,
                             _VP, _VP, _VP]),
     "gpcg_spmm": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP]),
@@ -464,7 +464,8 @@ class Batch:
     float64[n_bus_i]); the batch keeps them and re-reads their contents on
     every ``run()``.  ``out[i]`` holds grid i's device output tensors."""
 
-    def __init__(self, contexts, outages, rhs, block, tol=1e-12, max_iter=20000, *, flows=True, resid=True):
+    def __init__(self, contexts, outages, rhs, block, tol=1e-12, max_iter=20000, *, flows=True, resid=True,
+                 lookahead=0):
         import torch
 
         if not (len(contexts) == len(outages) == len(rhs)):
@@ -489,7 +490,8 @@ class Batch:
         self._keep = (ctxs, n_outs)
         h = C.c_void_p()
         _check(self._lib.gpcg_batch_create(
-            C.byref(h), k, ctxs, int(block), _ip(n_outs), _ptr_array(self.outages), _ptr_array(self.rhs),
+            C.byref(h), k, ctxs, int(block), int(lookahead), _ip(n_outs), _ptr_array(self.outages),
+            _ptr_array(self.rhs),
             float(tol), int(max_iter), _ptr_array([d["x"] for d in self.out]),
             _ptr_array([d["flows"] for d in self.out]), _ptr_array([d["iters"] for d in self.out]),
             _ptr_array([d["status"] for d in self.out]), _ptr_array([d["resid"] for d in self.out])))
@@ -513,13 +515,16 @@ class Batch:
 
 
 def batch_tune(contexts, outages, rhs, candidates=(4, 8, 16), tol=1e-12, max_iter=20000, reps=1):
-    """gpcg_batch_tune: milliseconds per batch solve for each candidate block."""
+    """gpcg_batch_tune: milliseconds per batch solve for each candidate tile
+    shape, a block or a (block, lookahead) pair."""
     k = len(contexts)
     ctxs = (C.c_void_p * k)(*[c._h.value for c in contexts])
     n_outs = np.array([int(o.shape[0]) for o in outages], np.int32)
-    cand = np.array(candidates, np.int32)
+    pairs = [(c, 0) if np.isscalar(c) else tuple(c) for c in candidates]
+    cand = np.array([b for b, _ in pairs], np.int32)
+    look = np.array([lk for _, lk in pairs], np.int32)
     ms = np.zeros(len(cand))
     _check(lib().gpcg_batch_tune(k, ctxs, _ip(n_outs), _ptr_array(outages), _ptr_array(rhs), float(tol),
-                                 int(max_iter), len(cand), _ip(cand), int(reps), _fp(ms)))
-    return dict(zip((int(c) for c in cand), (float(v) for v in ms)))
+                                 int(max_iter), len(cand), _ip(cand), _ip(look), int(reps), _fp(ms)))
+    return dict(zip(list(candidates), (float(v) for v in ms)))
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -645,7 +646,9 @@ struct gpcg_context {
     CsrH hA, hL, hU;                               // A, L, strict upper of U
     std::vector<double> h_invdiag;
     std::vector<int32_t> h_prerow;
-    std::shared_ptr<DevSchedule> sched_batched, sched_plain;  // shared with batches that use them
+    // sweep programs per (block, look-ahead window), shared with the batches
+    // that use them
+    std::map<std::pair<int, int>, std::shared_ptr<DevSchedule>> scheds;
     Topology topo;
     std::vector<double> theta_b_host;
     int base_iters = 0;
@@ -661,11 +664,19 @@ struct gpcg_context {
         if (ev1) (void)hipEventDestroy(ev1);
     }
 
-    DevSchedule &schedule_for(int S_) {
+    // The sweep programs for block S_ with a triangular look-ahead window of
+    // look_ rows (0: the context's), built once and kept.
+    std::shared_ptr<DevSchedule> schedule_ptr(int S_, int look_ = 0) {
+        if (look_ <= 0) look_ = look;
+        std::shared_ptr<DevSchedule> &slot = scheds[{S_, look_}];
+        if (!slot) slot = build_schedules(S_, look_);
+        return slot;
+    }
+    DevSchedule &schedule_for(int S_, int look_ = 0) { return *schedule_ptr(S_, look_); }
+
+    std::shared_ptr<DevSchedule> build_schedules(int S_, int look0) {
         const int R = gpcg::kWave / S_;
-        std::shared_ptr<DevSchedule> &slot = (S_ == 1) ? sched_plain : sched_batched;
-        if (slot && slot->R == R) return *slot;
-        auto D = std::make_unique<DevSchedule>();
+        auto D = std::make_shared<DevSchedule>();
         D->R = R;
         // ring rows + the zero row + the trash row must fit the LDS budget
         const int max_ring = std::max(1, gpcg::kLdsBudget / (int)(S_ * sizeof(double)) - 2);
@@ -676,7 +687,7 @@ struct gpcg_context {
             fail(GPCG_E_UNSUPPORTED, "the matrix bandwidth needs a larger LDS ring than a wavefront may use; "
                                      "give a banded row order (gpcg_options.perm, e.g. from gpcg_rcm) or set "
                                      "gpcg_options.reorder, or use a smaller block");
-        for (int look_try = look;; look_try /= 2) {
+        for (int look_try = look0;; look_try /= 2) {
             Schedule F = build_schedule(n_r, R, look_try, deps_f);
             Schedule B = build_schedule(n_r, R, look_try, deps_b);
             // the backward schedule was built on mirrored indices
@@ -698,8 +709,7 @@ struct gpcg_context {
                                          "give a banded row order (gpcg_options.perm, e.g. from gpcg_rcm) or set "
                                          "gpcg_options.reorder");
         }
-        slot = std::move(D);
-        return *slot;
+        return D;
     }
 
     gpcg::PcgParams params(const DevSchedule &D, const int32_t *outages, int n_out, const double *rhs, double tol,
@@ -1060,7 +1070,7 @@ namespace {
 
 // Build a batch without its graph: per grid the schedules for S, its own
 // workspace, the scenario order (once), the kernel parameters.
-std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, int max_iter) {
+std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, int max_iter, int look = 0) {
     if (sp.n < 1) fail(GPCG_E_ARG, "a batch needs at least one context");
     if (S < 1 || S > 64 || (S & (S - 1))) fail(GPCG_E_ARG, "block must be a power of two in [1, 64]");
     if (max_iter < 1) fail(GPCG_E_ARG, "max_iter must be >= 1");
@@ -1115,8 +1125,7 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
     long columns = 0;
     for (auto &G : b->g) {
         gpcg_context *h = G->ctx;
-        h->schedule_for(S);
-        G->sched = (S == 1) ? h->sched_plain : h->sched_batched;
+        G->sched = h->schedule_ptr(S, look);
         b->ring = std::max(b->ring, G->sched->ring_max());
         slot = std::max(slot, h->ws_slot(S));
         columns += G->tiles;
@@ -1793,7 +1802,8 @@ int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const do
     });
 }
 
-int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int32_t block, const int32_t *n_outs,
+int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int32_t block, int32_t lookahead,
+                      const int32_t *n_outs,
                       const int32_t *const *outages, const double *const *rhs, double tol, int32_t max_iter,
                       double *const *x_out, double *const *flows_out, int32_t *const *iters_out,
                       int32_t *const *status_out, double *const *resid_out) {
@@ -1812,7 +1822,8 @@ int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int3
         sp.resid_out = resid_out;
         sp.iters_out = iters_out;
         sp.status_out = status_out;
-        auto b = batch_build(sp, block, tol, max_iter);
+        if (lookahead < 0) fail(GPCG_E_ARG, "lookahead must be >= 0");
+        auto b = batch_build(sp, block, tol, max_iter, lookahead);
         // one eager solve (results valid at once), then the same work captured
         batch_enqueue(b.get());
         hip_check(hipStreamSynchronize(b->stream), "batch first solve");
@@ -1854,7 +1865,7 @@ void gpcg_batch_destroy(gpcg_batch_t b) {
 
 int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, const int32_t *const *outages,
                     const double *const *rhs, double tol, int32_t max_iter, int32_t n_cand, const int32_t *cand,
-                    int32_t reps, double *ms_out) {
+                    const int32_t *cand_look, int32_t reps, double *ms_out) {
     return guarded([&] {
         if (!ctxs || !n_outs || !outages || !rhs || !cand || !ms_out) fail(GPCG_E_ARG, "a required pointer is NULL");
         if (n_ctx < 1 || n_cand < 1 || reps < 1) fail(GPCG_E_ARG, "need contexts, candidates and reps >= 1");
@@ -1883,7 +1894,9 @@ int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, co
         sp.iters_out = ip.data();
         sp.status_out = spp.data();
         for (int k = 0; k < n_cand; ++k) {
-            auto b = batch_build(sp, cand[k], tol, max_iter);
+            const int look_k = cand_look ? cand_look[k] : 0;
+            if (look_k < 0) fail(GPCG_E_ARG, "lookahead must be >= 0");
+            auto b = batch_build(sp, cand[k], tol, max_iter, look_k);
             batch_enqueue(b.get());  // warm-up
             hipEvent_t e0, e1;
             hip_check(hipEventCreate(&e0), "event");

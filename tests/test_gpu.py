@@ -875,14 +875,15 @@ def test_batch_equals_single_solves_and_replays(gp, grids):
 
 def test_batch_uneven_grids_against_oracle(gp, grids):
     """The uneven workload's four smaller grids (500 to 3,000 buses, all 7,000
-    outages) in one batch, block chosen by the autotuner; 40 seeded outages
-    per grid against the oracle's direct solve."""
+    outages) in one batch, tile shape (block, look-ahead window) chosen by the
+    autotuner; 40 seeded outages per grid against the oracle's direct solve."""
     names = ["uneven500", "uneven1000", "uneven2000", "uneven3000"]
     ctxs, outs, rhs = _batch_inputs(gp, names, grids, 8)
     tuner = gp.BlockTuner()
-    S = tuner.best(ctxs, outs, rhs, candidates=(4, 8), tol=1e-12)
-    assert S in (4, 8) and tuner.best(ctxs, outs, rhs, candidates=(4, 8), tol=1e-12) == S
-    b = gp.Batch(ctxs, outs, rhs, block=S, tol=1e-12)
+    cands = ((4, 0), (8, 0), (8, 32))
+    S, look = tuner.best(ctxs, outs, rhs, candidates=cands, tol=1e-12)
+    assert (S, look) in cands and tuner.best(ctxs, outs, rhs, candidates=cands, tol=1e-12) == (S, look)
+    b = gp.Batch(ctxs, outs, rhs, block=S, tol=1e-12, lookahead=look)
     b.run()
     torch.cuda.synchronize()
     rng = np.random.default_rng(29)

@@ -215,3 +215,33 @@ def test_block_tuner_caches_and_persists(tmp_path, monkeypatch):
     t2 = autotune.BlockTuner(path)
     assert t2.best(ctxs, outs, None, (4, 8, 16)) == 8 and len(calls) == 1
     assert t2.best(ctxs, outs, None, (4, 8, 16), tol=1e-10) == 8 and len(calls) == 2  # another key
+
+
+def test_tuner_caches_tile_shapes(tmp_path, monkeypatch):
+    """(block, lookahead) candidates: the tuner returns the fastest pair,
+    and a cached pair comes back as a tuple after a JSON round trip."""
+    from paper_1803_03290_amd import autotune
+
+    class FakeCtx:
+        n_bus, kind = 6, 1
+        br_from = np.arange(5, dtype=np.int32)
+        br_to = np.arange(1, 6, dtype=np.int32)
+        x = np.full(5, 0.2)
+
+    class FakeOut:
+        shape = (3,)
+
+    calls = []
+    table = {(4, 16): 2.0, (8, 16): 1.0, (8, 64): 0.5, 8: 0.1}
+
+    def fake_tune(ctxs, outs, rhs, cands, tol, max_iter, reps):
+        calls.append(tuple(cands))
+        return {c: table[c] for c in cands}
+
+    monkeypatch.setattr(autotune, "batch_tune", fake_tune)
+    path = str(tmp_path / "tune.json")
+    cands = ((4, 16), (8, 16), (8, 64))
+    assert autotune.BlockTuner(path).best([FakeCtx()], [FakeOut()], None, cands) == (8, 64)
+    assert autotune.BlockTuner(path).best([FakeCtx()], [FakeOut()], None, cands) == (8, 64) and len(calls) == 1
+    # another candidate list is another key
+    assert autotune.BlockTuner(path).best([FakeCtx()], [FakeOut()], None, (8,)) == 8 and len(calls) == 2
