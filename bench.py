@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "N-1 scenario solves/sec to 1e-10 residual, batched vs plain PCG; HBM GB/s %"
 HBM_PEAK_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "pcg_tile_grid10k_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "pcg_wave_grid10k_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_tile.hip")
 
 # The method's algorithmic bytes per PCG iteration of one scenario: 15 vector
@@ -83,7 +83,7 @@ def auto_block(n_out: int) -> int:
 
 def read_counters():
     """(fetch_kib, write_kib, fetch_factor, write_factor, digest, (workload,
-    block)) from the
+    block, lookahead)) from the
     committed summary; each factor is what a plain copy of known size needs
     to turn that counter into bytes."""
     if not os.path.exists(COUNTERS):
@@ -96,7 +96,7 @@ def read_counters():
     try:
         return (float(vals["fetch_kib_per_dispatch"]), float(vals["write_kib_per_dispatch"]),
                 float(vals["fetch_copy_factor"]), float(vals["write_copy_factor"]), vals["kernel_digest"],
-                (vals["workload"], int(vals["block"])))
+                (vals["workload"], int(vals["block"]), int(vals.get("lookahead", "0"))))
     except KeyError:
         return None
 
@@ -320,6 +320,7 @@ UNEVEN = ("uneven500", "uneven1000", "uneven2000", "uneven3000", "uneven5000", "
 
 
 BATCH_SHAPES = ((4, 0), (8, 0), (16, 0), (8, 64), (8, 1024))
+BATCH_DEFAULT_SHAPE = (4, 0)  # the autotuner's pick over BATCH_SHAPES on the uneven workload
 
 
 def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN, shapes=BATCH_SHAPES):
@@ -346,10 +347,13 @@ def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNE
     outs = [torch.arange(g.m, dtype=torch.int32, device=dev) for g in grids]
     rhs = [torch.tensor(g.P, dtype=torch.float64, device=dev) for g in grids]
     tune_ms = {}
-    for cand in shapes:  # the autotuner's search, one candidate per call so that progress shows
-        tune_ms.update(gp.batch_tune(ctxs, outs, rhs, (cand,), tol, max_iter))
-        progress(f"block {cand[0]}, look-ahead {cand[1] or 'default'}: {tune_ms[cand]:.1f} ms per solve")
-    S, look = min(tune_ms, key=tune_ms.get)
+    if len(shapes) > 1:
+        for cand in shapes:  # the autotuner's search, one candidate per call so that progress shows
+            tune_ms.update(gp.batch_tune(ctxs, outs, rhs, (cand,), tol, max_iter))
+            progress(f"block {cand[0]}, look-ahead {cand[1] or 'default'}: {tune_ms[cand]:.1f} ms per solve")
+        S, look = min(tune_ms, key=tune_ms.get)
+    else:
+        S, look = shapes[0]
     b = gp.Batch(ctxs, outs, rhs, block=S, tol=tol, max_iter=max_iter, flows=True, lookahead=look)
     b.run()
     torch.cuda.synchronize()
@@ -369,7 +373,7 @@ def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNE
     return {"workload": f"uneven batch: {len(grids)} grids of {grids[0].n} to {grids[-1].n} buses, all {n} outages "
                         f"in one graph-captured launch, tol {tol:g}",
             "value": n / (ms * 1e-3), "unit": "scenarios/s", "ms": ms, "block": S, "lookahead": look,
-            "tuner_ms_per_solve": {f"{b}/{lk}": v for (b, lk), v in tune_ms.items()},
+            "tuner_ms_per_solve": {f"{b}/{lk}": v for (b, lk), v in tune_ms.items()} or None,
             "max_true_rel_residual": resid,
             "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
 
@@ -382,6 +386,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="grid10k", help="grid spec key (grid200, grid2k, grid10k, ...)")
     ap.add_argument("--block", type=int, default=8, help="scenarios per tile (0: auto)")
+    ap.add_argument("--lookahead", type=int, default=0,
+                    help="look-ahead window of the triangular schedules, rows (0: the library's 256)")
     ap.add_argument("--tol", type=float, default=1e-12,
                     help="stop on the recursive relative residual; on the 10k grid 1e-12 meets both the 1e-10 "
                          "true-residual bar and the 1e-8 rad angle bar on every outage")
@@ -406,7 +412,9 @@ def main():
     ap.add_argument("--ablation-workload", default="grid2k", help="grid of the ablations (Jacobi, x0 = 0)")
     ap.add_argument("--ablation-block", type=int, default=4)
     ap.add_argument("--batch", action="store_true",
-                    help="also run the uneven multi-grid batch (72,100 outages of eight grids; several minutes)")
+                    help="run the uneven multi-grid batch with the autotuner's search over five tile shapes "
+                         "(several minutes) instead of at the shape it picks on this workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven multi-grid batch")
     ap.add_argument("--batch-only", action="store_true", help="only the uneven multi-grid batch")
     ap.add_argument("--fdpf-workload", default="grid10k", help="grid of the power-flow measurement")
     ap.add_argument("--fdpf-only", action="store_true", help="only the power-flow measurement")
@@ -473,7 +481,7 @@ def main():
         return
     t0 = time.perf_counter()
     block = args.block or auto_block(grid.m)
-    ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=block)
+    ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=block, lookahead=args.lookahead)
     setup_s = time.perf_counter() - t0
     info = ctx.info()
     m = grid.m
@@ -536,7 +544,7 @@ def main():
         del aout
     traffic = None
     cnt = read_counters()
-    if cnt and cnt[4] == kernel_digest() and cnt[5] == (args.workload, S):
+    if cnt and cnt[4] == kernel_digest() and cnt[5] == (args.workload, S, args.lookahead):
         traffic = cnt[0] * 1024.0 * cnt[2] + cnt[1] * 1024.0 * cnt[3]
 
     plain = None
@@ -569,7 +577,11 @@ def main():
     progress("spmm, adjoint and power-flow legs done")
     abl = None if args.no_ablations else ablation_measure(gp, torch, aux_grid(args.ablation_workload),
                                                           args.ablation_block, 5e-11, args.max_iter)
-    bat = batch_measure(gp, torch, args.tol, args.max_iter) if args.batch else None
+    bat = None
+    if not args.no_batch:
+        # the whole uneven workload (72,100 outages); by default at the tile shape the autotuner picks on it
+        bat = batch_measure(gp, torch, args.tol, args.max_iter, reps=1,
+                            shapes=BATCH_SHAPES if args.batch else (BATCH_DEFAULT_SHAPE,))
 
     value = m / (ms_step * 1e-3)
     st_counts = {int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))}
@@ -589,8 +601,8 @@ def main():
         "config": {
             "workload": f"{grid.name}: {grid.n}-bus synthetic grid, all {m} N-1 branch outages, batched PCG with "
                         f"base-case ILU(0), FP64, recursive residual stop {args.tol:g}, true residual <= 1e-10",
-            "n_bus": grid.n, "n_branches": m, "scenarios": m, "block": S, "tol": args.tol,
-            "grid_sha256": grid.digest()[:16],
+            "n_bus": grid.n, "n_branches": m, "scenarios": m, "block": S, "lookahead": args.lookahead or 256,
+            "tol": args.tol, "grid_sha256": grid.digest()[:16],
         },
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "plain": plain,

@@ -418,10 +418,15 @@ int gpcg_screen_overloads(gpcg_t h, int32_t n_out, const double *flows, const do
  * on to the smaller ones; the launch is captured once in a HIP graph
  * together with each grid's base-state residual and output kernels.
  *   gpcg_batch_create  builds the batch (schedules for S, its own
- *                      workspace and scenario order per grid), runs one
+ *                      workspace and scenario queues per grid), runs one
  *                      solve eagerly, captures the graph;
- *   gpcg_batch_run     replays the graph (reads the current contents of the
- *                      input buffers, overwrites the outputs);
+ *   gpcg_batch_run     ranks each grid's queue, then replays the graph
+ *                      (reads the current contents of the input buffers,
+ *                      overwrites the outputs).
+ * Each solve ranks a grid's queue as gpcg_solve_contingencies does, by the
+ * iterations each outage took in the context's previous solve, batch or
+ * single (the ranking runs on the batch's stream before the graph), and
+ * the graph records this solve's iterations for the next.
  *   gpcg_batch_destroy frees the batch (the contexts must outlive it).
  * flows_out and resid_out may be NULL (or hold NULL entries).  The batch
  * works on a stream of its own ordered after and before the contexts'

@@ -1027,6 +1027,12 @@ struct BatchGrid {
     int32_t *iters_out = nullptr, *status_out = nullptr;
     DevBuf<double> rho_b, gfac;
     DevBuf<int32_t> order, pos;
+    // ranking of the scenario queue (rebuilt before every solve from the
+    // context's per-outage iteration record)
+    DevBuf<uint32_t> keys, keys_sorted;
+    DevBuf<int32_t> iota;
+    DevBuf<char> temp;
+    size_t temp_bytes = 0;
 };
 
 struct BatchSpec {
@@ -1153,23 +1159,15 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
         p.x_out = G->x_out;
         p.zero_start = h->zero_start;
         p.add_base = h->zero_start ? 0 : 1;
-        if (S > 1 && G->n_out > S) {
+        if (needs_order(S, G->n_out)) {
             const int n = G->n_out;
-            DevBuf<uint32_t> keys, keys_sorted;
-            DevBuf<int32_t> iota;
-            DevBuf<char> temp;
-            keys.alloc(n);
-            keys_sorted.alloc(n);
-            iota.alloc(n);
+            G->keys.alloc(n);
+            G->keys_sorted.alloc(n);
+            G->iota.alloc(n);
             G->order.alloc(n);
             G->pos.alloc(n);
-            const size_t tb = gpcg::sort_temp_bytes(n);
-            temp.alloc(std::max<size_t>(tb, 1));
-            hip_check(gpcg::launch_order(n, G->outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
-                                         h->isl_hi.p, h->theta_b.p, h->hist_base.p, keys.p, keys_sorted.p, iota.p,
-                                         G->order.p, G->pos.p, temp.p, tb, b->stream),
-                      "scenario ordering");
-            hip_check(hipStreamSynchronize(b->stream), "ordering");
+            G->temp_bytes = gpcg::sort_temp_bytes(n);
+            G->temp.alloc(std::max<size_t>(G->temp_bytes, 1));
             p.order = G->order.p;
         }
         prm.push_back(p);
@@ -1177,6 +1175,21 @@ std::unique_ptr<gpcg_batch> batch_build(const BatchSpec &sp, int S, double tol, 
     b->params.upload(prm.data(), prm.size(), b->stream);
     hip_check(hipStreamSynchronize(b->stream), "batch upload");
     return b;
+}
+
+// Rank every grid's scenario queue, most expected work first: by the
+// iterations each outage took in its context's previous solve (batch or
+// single), by the analytic key where there is no record.  Enqueued before
+// each solve, outside the captured graph (the sort is a library call).
+void batch_order(gpcg_batch *b) {
+    for (auto &G : b->g) {
+        if (!G->order.p) continue;
+        gpcg_context *h = G->ctx;
+        hip_check(gpcg::launch_order(G->n_out, G->outages, h->m, h->br_from.p, h->br_to.p, h->br_b.p, h->isl_lo.p,
+                                     h->isl_hi.p, h->theta_b.p, h->hist_base.p, G->keys.p, G->keys_sorted.p,
+                                     G->iota.p, G->order.p, G->pos.p, G->temp.p, G->temp_bytes, b->stream),
+                  "scenario ordering");
+    }
 }
 
 // Everything one solve of the batch enqueues (what the graph captures):
@@ -1191,6 +1204,12 @@ void batch_enqueue(gpcg_batch *b) {
     }
     hip_check(gpcg::launch_pcg_multi(b->params.p, (int)b->g.size(), b->S, b->n_waves, b->ring, b->stream),
               "batch launch");
+    for (auto &G : b->g) {
+        if (!G->order.p) continue;
+        hip_check(gpcg::launch_record_iters(G->n_out, G->outages, G->ctx->m, G->iters_out, G->ctx->hist_base.p,
+                                            b->stream),
+                  "iteration records");
+    }
     for (auto &G : b->g) {
         gpcg_context *h = G->ctx;
         if (G->n_out == 0) continue;
@@ -1825,6 +1844,7 @@ int gpcg_batch_create(gpcg_batch_t *out, int32_t n_ctx, const gpcg_t *ctxs, int3
         if (lookahead < 0) fail(GPCG_E_ARG, "lookahead must be >= 0");
         auto b = batch_build(sp, block, tol, max_iter, lookahead);
         // one eager solve (results valid at once), then the same work captured
+        batch_order(b.get());
         batch_enqueue(b.get());
         hip_check(hipStreamSynchronize(b->stream), "batch first solve");
         hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -1850,6 +1870,7 @@ int gpcg_batch_run(gpcg_batch_t b) {
         hip_check(hipSetDevice(b->device), "hipSetDevice");
         hip_check(hipEventRecord(b->ev_in, b->outer), "event");
         hip_check(hipStreamWaitEvent(b->stream, b->ev_in, 0), "stream wait");
+        batch_order(b);
         hip_check(hipGraphLaunch(b->exec, b->stream), "graph launch");
         hip_check(hipEventRecord(b->ev_out, b->stream), "event");
         hip_check(hipStreamWaitEvent(b->outer, b->ev_out, 0), "stream wait");
@@ -1897,12 +1918,16 @@ int gpcg_batch_tune(int32_t n_ctx, const gpcg_t *ctxs, const int32_t *n_outs, co
             const int look_k = cand_look ? cand_look[k] : 0;
             if (look_k < 0) fail(GPCG_E_ARG, "lookahead must be >= 0");
             auto b = batch_build(sp, cand[k], tol, max_iter, look_k);
+            batch_order(b.get());
             batch_enqueue(b.get());  // warm-up
             hipEvent_t e0, e1;
             hip_check(hipEventCreate(&e0), "event");
             hip_check(hipEventCreate(&e1), "event");
             hip_check(hipEventRecord(e0, b->stream), "event");
-            for (int r = 0; r < reps; ++r) batch_enqueue(b.get());
+            for (int r = 0; r < reps; ++r) {
+                batch_order(b.get());
+                batch_enqueue(b.get());
+            }
             hip_check(hipEventRecord(e1, b->stream), "event");
             hip_check(hipEventSynchronize(e1), "event sync");
             float ms = 0.0f;
