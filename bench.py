@@ -286,7 +286,8 @@ def fdpf_measure(gp, torch, grid, S: int = 8, scale: float = 1e-4, n_outer: int 
 def ablation_measure(gp, torch, grid, S: int, tol: float, max_iter: int, steps: int = 3):
     """The paper's own alternatives, same kernels: the Jacobi preconditioner
     of the GPCG listing and the zero start of the PCG listing, against the
-    base-case ILU(0) and the base-state start.  Run on the grid given
+    base-case ILU(0) and the base-state start (``base_ilu0``, the method
+    itself on the same grid and block).  Run on the grid given
     (normally the 2,000-bus grid: Jacobi takes about 13 times the base-ILU
     iterations, too long a leg on the 10k grid)."""
     import numpy as np
@@ -295,7 +296,7 @@ def ablation_measure(gp, torch, grid, S: int, tol: float, max_iter: int, steps: 
     outs = torch.arange(grid.m, dtype=torch.int32, device=dev)
     rhs = torch.tensor(grid.P, dtype=torch.float64, device=dev)
     res = {}
-    for name, kw in (("jacobi", dict(precond="jacobi")), ("zero_start", dict(zero_start=True))):
+    for name, kw in (("base_ilu0", {}), ("jacobi", dict(precond="jacobi")), ("zero_start", dict(zero_start=True))):
         ctx = gp.Context(grid.n, grid.br_from, grid.br_to, grid.x, grid.P, block=S, **kw)
         out = ctx.solve(outs, rhs, tol=tol, max_iter=max_iter)
         torch.cuda.synchronize()
@@ -320,7 +321,7 @@ UNEVEN = ("uneven500", "uneven1000", "uneven2000", "uneven3000", "uneven5000", "
 
 
 BATCH_SHAPES = ((4, 0), (8, 0), (16, 0), (8, 64), (8, 1024))
-BATCH_DEFAULT_SHAPE = (4, 0)  # the autotuner's pick over BATCH_SHAPES on the uneven workload
+BATCH_DEFAULT_SHAPE = (8, 0)  # the autotuner's pick over BATCH_SHAPES on the uneven workload
 
 
 def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN, shapes=BATCH_SHAPES):
