@@ -386,8 +386,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="grid10k", help="grid spec key (grid200, grid2k, grid10k, ...)")
-    ap.add_argument("--block", type=int, default=8, help="scenarios per tile (0: auto)")
-    ap.add_argument("--lookahead", type=int, default=0,
+    ap.add_argument("--block", type=int, default=4, help="scenarios per wavefront (0: auto)")
+    ap.add_argument("--lookahead", type=int, default=64,
                     help="look-ahead window of the triangular schedules, rows (0: the library's 256)")
     ap.add_argument("--tol", type=float, default=1e-12,
                     help="stop on the recursive relative residual; on the 10k grid 1e-12 meets both the 1e-10 "
