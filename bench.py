@@ -287,7 +287,8 @@ def ablation_measure(gp, torch, grid, S: int, tol: float, max_iter: int, steps: 
     """The paper's own alternatives, same kernels: the Jacobi preconditioner
     of the GPCG listing and the zero start of the PCG listing, against the
     base-case ILU(0) and the base-state start (``base_ilu0``, the method
-    itself on the same grid and block).  Run on the grid given
+    itself on the same grid and block), and the plain per-scenario PCG over
+    the grid's whole outage list beside it.  Run on the grid given
     (normally the 2,000-bus grid: Jacobi takes about 13 times the base-ILU
     iterations, too long a leg on the 10k grid)."""
     import numpy as np
@@ -313,6 +314,22 @@ def ablation_measure(gp, torch, grid, S: int, tol: float, max_iter: int, steps: 
         res[name] = {"value": grid.m / (ms * 1e-3), "unit": "scenarios/s", "ms": ms,
                      "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                      "max_true_rel_residual": float(out["resid"].max().item())}
+        if name == "base_ilu0":
+            # the plain per-scenario PCG over the whole outage list of this grid
+            ctx.solve(outs[:16], rhs, tol=tol, max_iter=max_iter, plain=True)  # warm-up
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            pout = ctx.solve(outs, rhs, tol=tol, max_iter=max_iter, plain=True)
+            e1.record(ctx.stream)
+            torch.cuda.synchronize()
+            p_ms = e0.elapsed_time(e1)
+            res["plain_all_outages"] = {
+                "value": grid.m / (p_ms * 1e-3), "unit": "scenarios/s", "ms": p_ms,
+                "iters_mean": float(pout["iters"].float().mean().item()),
+                "max_abs_diff_vs_batched_rad": float((pout["x"] - out["x"]).abs().max().item()),
+                "batched_vs_plain": (grid.m / (ms * 1e-3)) / (grid.m / (p_ms * 1e-3))}
+            del pout
     return res
 
 
@@ -386,7 +403,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="grid10k", help="grid spec key (grid200, grid2k, grid10k, ...)")
-    ap.add_argument("--block", type=int, default=4, help="scenarios per wavefront (0: auto)")
+    ap.add_argument("--block", type=int, default=16, help="scenarios per wavefront (0: auto)")
     ap.add_argument("--lookahead", type=int, default=64,
                     help="look-ahead window of the triangular schedules, rows (0: the library's 256)")
     ap.add_argument("--tol", type=float, default=1e-12,

@@ -34,15 +34,24 @@ namespace gpcg {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Sweeps.  Each sweep walks its program step by step through a three-stage
-// register pipeline: a step's row record is loaded H = 2D steps ahead, its
-// vector rows D steps ahead and its matrix entries E steps ahead (8 in the
-// triangular solves, 2 in the product; they are shared by every wave and
-// sit in L1/L2; vector-memory counters retire in order, so the wait for a
-// step's entries also waits for every older load).  A step first consumes its
-// pipeline slots and then refills them with later steps, so no register is
-// copied, no load waits on another load still in flight, and a step only
+// Sweeps.  Each sweep walks its program step by step through a register
+// pipeline: a step's row record is loaded H = 2D steps ahead, its vector rows
+// D steps ahead and its matrix entries ahead of those (shared by every wave,
+// they sit in L1/L2; vector-memory counters retire in order, so the wait for
+// a step's entries also waits for every older load).  A step first consumes
+// its pipeline slots and then refills them with later steps, so no register
+// is copied, no load waits on another load still in flight, and a step only
 // waits on the LDS ring that carries the dependencies between rows.
+//
+// The entries of a step serve the S column lanes of each row slot alike.
+// Where a step's entry chunks fit two loads per lane (S >= 4), each chunk is
+// loaded once: lane l loads chunk l of the step (EQ steps before it is
+// needed), writes it to a per-wave LDS staging area, and every lane reads its
+// slot's chunks back from there LA steps before the step runs.  This cuts
+// the vector-memory instructions and lane traffic of the entries by the
+// factor S (they had been the larger part of the sweeps' vector-memory
+// work); LDS, otherwise lightly used, carries the copies.  Smaller blocks
+// load each slot's chunks per lane directly.
 // Vector-memory counters complete in order, so the loop has no branches
 // around loads and stores: idle slots read and write the tile's scratch row
 // (row n_r; it holds r = 0 and p = 0, and q = 0 when the forward sweep reads
@@ -54,8 +63,8 @@ namespace {
 // pairs), and every sweep reads only the vectors it needs.  Vector bases are
 // wave-uniform (scalar registers); a step computes one 32-bit offset for all
 // of them (twice it for the pairs).
-constexpr int kEntAheadTri = 8;   // steps the triangular solves prefetch entries
-constexpr int kEntAheadProd = 2;  // steps the product prefetches entries
+constexpr int kEntAheadTri = 8;   // steps the triangular solves load entries ahead (staged: before the LDS copy)
+constexpr int kEntAheadProd = 2;  // steps the product loads entries ahead (direct form)
 
 // The step index as a vector register the compiler cannot see through.
 // Without it a wave-uniform index makes the loaded row id uniform too, and
@@ -79,6 +88,7 @@ __device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
 // byte offsets.  Chunk c of every slot of a step is stored contiguously, so
 // each chunk is one coalesced 16-byte load into an aligned register group.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef int ivec4 __attribute__((ext_vector_type(4)));
 
 template <int K>
 struct Ents {
@@ -133,6 +143,53 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
 #pragma unroll
     for (int j = 0; j < K; ++j) acc += G.v[j] * G.r[j];
     return acc;
+}
+
+// ---- staged entries --------------------------------------------------------
+// A step's NC = C R entry chunks, loaded once each: load i of lane l takes
+// chunk (i kWave + l) mod NC, so NL loads cover the step (lanes past NC
+// repeat chunks of the same step and write them to unused staging rows).
+// The staging area holds NL kWave chunks; a wave writes it and reads it back
+// in program order, and its LDS instructions complete in order, so one area
+// per wave serves every step.
+constexpr int kStageChunks = 2 * kWave;  // 16-byte chunks of a wave's staging area
+
+template <int S, int K>
+struct Stage {
+    static constexpr int R = kWave / S, C = 3 * K / 4, NC = C * R, NL = (NC + kWave - 1) / kWave;
+    static constexpr bool kOn = NL * kWave <= kStageChunks;
+};
+
+// the chunks of a step lane l loads: i kWave + l, wrapped into the step
+template <int S, int K>
+struct StageLane {
+    int j[Stage<S, K>::NL];
+    __device__ __forceinline__ explicit StageLane(int lane) {
+#pragma unroll
+        for (int i = 0; i < Stage<S, K>::NL; ++i) j[i] = (i * kWave + lane) % Stage<S, K>::NC;
+    }
+};
+
+template <int S, int K>
+__device__ __forceinline__ void raw_load(ivec4 *q, const int4 *step_base, const StageLane<S, K> &L) {
+#pragma unroll
+    for (int i = 0; i < Stage<S, K>::NL; ++i) q[i] = *(const ivec4 *)(step_base + L.j[i]);
+}
+
+template <int S, int K>
+__device__ __forceinline__ void raw_put(int4 *stage, const ivec4 *q, int lane) {
+#pragma unroll
+    for (int i = 0; i < Stage<S, K>::NL; ++i) ((ivec4 *)stage)[i * kWave + lane] = q[i];
+}
+
+// entries of slot rs from the staging area (chunk c of slot rs at c R + rs)
+template <int S, int K>
+__device__ __forceinline__ void stage_read(Ents<K> &E, const int4 *stage, int rs) {
+    constexpr int R = kWave / S;
+#pragma unroll
+    for (int c = 0; c < K / 2; ++c) E.v[c] = *(const dvec2 *)(stage + c * R + rs);
+#pragma unroll
+    for (int c = 0; c < K / 4; ++c) E.o[c] = stage[(K / 2 + c) * R + rs];
 }
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
@@ -250,8 +307,8 @@ __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T,
 }
 
 template <int S, int D>
-__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
-                                            double alpha) {
+__device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                                   double alpha) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
     static_assert(2 * H - 1 <= kPadSteps, "prefetch past the last step must stay in the padding");
@@ -314,6 +371,95 @@ __device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, cons
     return rr;
 }
 
+template <int S, int D>
+__device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+                                                   int rs, int sc, double alpha) {
+    constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
+    using St = Stage<S, K>;
+    constexpr int R = St::R, NC = St::NC, NL = St::NL;
+    constexpr int NE = 4, LA = 3;  // entry register slots; entries read from LDS LA steps ahead of use
+    static_assert(H % EQ == 0 && H % NE == 0 && EQ >= 1, "entry slots must tile the unrolled loop");
+    static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
+                  "prefetch past the last step must stay in the padding");
+    const int lane = threadIdx.x;
+    const StageLane<S, K> L(lane);
+    const int z0 = opaque(0);
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rr = 0.0, carry = 0.0;
+    int4 hq[H];
+    FwdVec vq[D];
+    ivec4 q[EQ][NL];   // raw chunks of steps LA .. LA + EQ - 1 ahead
+    Ents<K> eq[NE];    // entries of steps d .. d + LA
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
+    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+#pragma unroll
+    for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < LA; ++d) {
+        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_put<S, K>(stage, q[0], lane);
+        stage_read<S, K>(eq[d], stage, rs);
+    }
+#pragma unroll
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double r = vq[0].r - alpha * vq[0].q;  // step 0's residual row
+    double rc = r;                         // ... minus its carry
+    fwd_vec<S>(vq[0], hq[D], T, sc);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);  // step base: every address below is a constant offset from it
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *qb = g.ent + (size_t)sb * NC;
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int4 h = hq[d];
+            asm volatile("" ::"v"(h.z));  // unused here; keeps the record one 16-byte load
+            // A
+            const double dot = tree_dot(G, eq[d % NE]);
+            const double y = rc - dot;
+            ring_put(ring, h.y + lane_off, y);
+            ring_addr(ga, eq[(d + 1) % NE], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
+            {
+                const unsigned o = sweep_off<S>(T, h.x, sc);
+                const bool cont = h.w == 1;
+                ry_put(T, o, r, cont ? 0.0 : y);
+                rr = __builtin_fma(r, r, rr);
+                carry = cont ? carry + dot : 0.0;
+                const FwdVec v = vq[(d + 1) % D];
+                r = v.r - alpha * v.q;
+                rc = r - carry;
+            }
+            // step d + LA: raw chunks to LDS, its entries back into the slot
+            // step d - 1 used; then the raw slot takes step d + LA + EQ
+            raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
+            stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
+            fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            hq[d] = hb[(d + H) * R];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rr;
+}
+
+template <int S, int D>
+__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+                                            int sc, double alpha) {
+    if constexpr (Stage<S, kEntTri>::kOn)
+        return fwd_sweep_staged<S, D>(g, ring, stage, T, rs, sc, alpha);
+    else
+        return fwd_sweep_direct<S, D>(g, ring, T, rs, sc, alpha);
+}
+
 // ---- backward: z = U^-1 y, islanded rows zeroed on output, r'z ------------
 // Its records are packed: {row | slot << 20, pre | (aux + 1) << 20, 1 / U_ii}.
 __device__ __forceinline__ int bwd_row(const int4 &h) { return h.x & kBwdRowMask; }
@@ -337,8 +483,8 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile &T,
     v.r = ry.x;
 }
 template <int S, int D>
-__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc, int lo,
-                                            int hi) {
+__device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+                                                   int lo, int hi) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
     static_assert(2 * H - 1 <= kPadSteps, "prefetch past the last step must stay in the padding");
@@ -398,6 +544,92 @@ __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, cons
     return rz;
 }
 
+template <int S, int D>
+__device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+                                                   int rs, int sc, int lo, int hi) {
+    constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
+    using St = Stage<S, K>;
+    constexpr int R = St::R, NC = St::NC, NL = St::NL;
+    constexpr int NE = 4, LA = 3;
+    static_assert(H % EQ == 0 && H % NE == 0 && EQ >= 1, "entry slots must tile the unrolled loop");
+    static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
+                  "prefetch past the last step must stay in the padding");
+    const int lane = threadIdx.x;
+    const StageLane<S, K> L(lane);
+    const int z0 = opaque(0);
+    const int lane_off = sc * 8;
+    if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
+    double rz = 0.0, carry = 0.0;
+    int4 hq[H];
+    BwdVec vq[D];
+    ivec4 q[EQ][NL];
+    Ents<K> eq[NE];
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
+    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+#pragma unroll
+    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < LA; ++d) {
+        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_put<S, K>(stage, q[0], lane);
+        stage_read<S, K>(eq[d], stage, rs);
+    }
+#pragma unroll
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    int ga[K];
+    double G[K];
+    ring_addr(ga, eq[0], lane_off);
+    ring_read(G, ga, ring);
+    double yc = vq[0].y, dv = bwd_dinv(hq[0]), r = vq[0].r;  // step 0's row
+    bwd_vec<S>(vq[0], hq[D], T, sc);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *qb = g.ent + (size_t)sb * NC;
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int4 h = hq[d];
+            // A
+            const double dot = tree_dot(G, eq[d % NE]);
+            const double z = (yc - dot) * dv;
+            ring_put(ring, bwd_own<S>(h) + lane_off, z);
+            ring_addr(ga, eq[(d + 1) % NE], lane_off);
+            ring_read(G, ga, ring);
+            __builtin_amdgcn_sched_barrier(0);
+            // B
+            {
+                const int row = bwd_row(h);
+                const double zm = in_interval(bwd_pre(h), lo, hi) ? 0.0 : z;
+                y_put(T, sweep_off<S>(T, row, sc), zm);
+                rz = __builtin_fma(r, zm, rz);
+                carry = bwd_cont(h) ? carry + dot : 0.0;
+                const BwdVec v = vq[(d + 1) % D];
+                yc = v.y - carry;
+                dv = bwd_dinv(hq[(d + 1) % H]);
+                r = v.r;
+            }
+            raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
+            stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
+            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            hq[d] = hb[(d + H) * R];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return rz;
+}
+
+template <int S, int D>
+__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+                                            int sc, int lo, int hi) {
+    if constexpr (Stage<S, kEntTri>::kOn)
+        return bwd_sweep_staged<S, D>(g, ring, stage, T, rs, sc, lo, hi);
+    else
+        return bwd_sweep_direct<S, D>(g, ring, T, rs, sc, lo, hi);
+}
+
 // ---- product: on the look-ahead row delta += alpha p_old and p = z + beta
 // p_old (into the ring and memory); on the current row q = A_c p from the
 // ring with the outaged branch shielded, and p'q.  Natural row order.
@@ -415,7 +647,7 @@ __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &
 }
 
 template <int S, int D>
-__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, const Tile &T, int rs, int sc,
+__device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                              double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
                                              double bc) {
     constexpr int H = 2 * D, E = kEntAheadProd;
@@ -480,6 +712,103 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, con
         }
     }
     return pq;
+}
+
+template <int S, int D>
+__device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+                                                    int rs, int sc,
+                                             double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
+                                             double bc) {
+    constexpr int H = 2 * D, K = kEntProd;
+    using St = Stage<S, K>;
+    constexpr int R = St::R, NC = St::NC, NL = St::NL;
+    constexpr int NE = 2, LA = 2, EQ = 2;  // entry slots, LDS read-ahead, raw-load distance
+    static_assert(H % EQ == 0 && H % NE == 0, "entry slots must tile the unrolled loop");
+    static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
+                  "prefetch past the last step must stay in the padding");
+    const int lane = threadIdx.x;
+    const StageLane<S, K> L(lane);
+    const int z0 = opaque(0);
+    const int lane_off = sc * 8;
+    const int wm = g.ring - 1;
+    const int zero = g.ring * S * 8;
+    const int trash = (g.ring + 1) * S * 8;
+    if (rs == 0) ring_put(ring, zero + lane_off, 0.0);
+    const int ic_off = ((ic >= 0) ? (ic & wm) * S * 8 : zero) + lane_off;
+    const int jc_off = ((jc >= 0) ? (jc & wm) * S * 8 : zero) + lane_off;
+    double pq = 0.0, carry = 0.0;
+    int4 hq[H];
+    ProdVec vq[D];
+    ivec4 q[EQ][NL];
+    Ents<K> eq[NE];
+    const int4 *hb0 = head_slot<S>(g, z0, rs);
+    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+#pragma unroll
+    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+#pragma unroll
+    for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
+#pragma unroll
+    for (int d = 0; d < LA; ++d) {
+        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_put<S, K>(stage, q[0], lane);
+        stage_read<S, K>(eq[d], stage, rs);
+    }
+#pragma unroll
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    for (int s0 = 0; s0 < g.steps; s0 += H) {
+        const int sb = opaque(s0);  // step base: every address below is a constant offset from it
+        const int4 *hb = head_slot<S>(g, sb, rs);
+        const int4 *qb = g.ent + (size_t)sb * NC;
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            const int4 h = hq[d];
+            const ProdVec v = vq[d % D];
+            // look-ahead row: pending solution update and new direction (its
+            // ring write must precede this step's reads)
+            const unsigned lo_ = sweep_off<S>(T, h.w, sc);
+            const double pn = done ? v.p : v.z + beta * v.p;
+            ring_put(ring, ((h.w < T.nr) ? (h.w & wm) * S * 8 : trash) + lane_off, pn);
+            Gath<K> G;
+            gather(G, eq[d % NE], ring, lane_off);
+            const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
+            const double pown = ring_at(ring, h.y + lane_off);
+            prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
+            // step d + LA: raw chunks to LDS, its entries into the slot this
+            // step's gather has read; the raw slot takes step d + LA + EQ
+            raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
+            stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
+            hq[d] = hb[(d + H) * R];
+            {
+                xp_put(T, lo_, v.x + alpha * v.p, pn);
+                const double dot = gdot(G);
+                const bool cont = h.z == -2;
+                double qv = carry + dot;
+                carry = cont ? carry + dot : 0.0;
+                const double dpc = pf - pt;
+                qv += (h.x == ic) ? -bc * dpc : ((h.x == jc) ? bc * dpc : 0.0);
+                // a continuation's partial sum is not stored, so the scratch
+                // row's q, as the forward sweep reads it, is exactly zero
+                // (and with it its r); islanded rows are zero
+                if (in_interval(h.z, lo, hi)) qv = 0.0;
+                qv = cont ? 0.0 : qv;
+                y_put(T, sweep_off<S>(T, h.x, sc), qv);  // z of this row was read as a look-ahead row
+                pq = __builtin_fma(pown, qv, pq);  // idle slots read pown from the zero row
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return pq;
+}
+
+template <int S, int D>
+__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+                                             int sc, double alpha, double beta, bool done, int lo, int hi, int ic,
+                                             int jc, double bc) {
+    if constexpr (Stage<S, kEntProd>::kOn)
+        return prod_sweep_staged<S, D>(g, ring, stage, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc);
+    else
+        return prod_sweep_direct<S, D>(g, ring, T, rs, sc, alpha, beta, done, lo, hi, ic, jc, bc);
 }
 
 // delta += alpha p over every row (the update the product sweep would have
@@ -693,6 +1022,9 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
     T.w = T.v[3];
     T.nr = p.n_r;
     T.idle = false;
+    // entry staging after the rings (the launch sizes LDS for the largest)
+    const int ring_rows = max(p.fwd.ring, max(p.bwd.ring, p.prod.ring));
+    int4 *stage = (int4 *)((char *)ring + ((((size_t)ring_rows + 2) * S * 8 + 15) & ~(size_t)15));
     if (rs == 0) {  // the scratch row holds zeros for idle slots
         const unsigned o = row_off<S>(T, p.n_r, sc);
         xp_put(T, o, 0.0, 0.0);
@@ -708,7 +1040,7 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
         __syncthreads();
         ++sweeps;
         // ---- forward sweep: r -= alpha q, y = L^-1 r ----------------------
-        double rrp = fwd_sweep<S, D>(p.fwd, ring, T, rs, sc, alpha);
+        double rrp = fwd_sweep<S, D>(p.fwd, ring, stage, T, rs, sc, alpha);
         __syncthreads();
         rrp = col_sum<S>(rrp);
         if (col.scen >= 0 && !done) {
@@ -736,14 +1068,15 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
         }
 
         // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
-        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, T, rs, sc, col.lo, col.hi));
+        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, stage, T, rs, sc, col.lo, col.hi));
         __syncthreads();
         const double beta = (col.k == 0 || done) ? 0.0 : rz / rho;
         rho = rz;
 
         // ---- p = z + beta p and q = A_c p (outaged branch shielded), p'q ---
         const double sigma = col_sum<S>(
-            prod_sweep<S, DP>(p.prod, ring, T, rs, sc, alpha, beta, done, col.lo, col.hi, col.ic, col.jc, col.bc));
+            prod_sweep<S, DP>(p.prod, ring, stage, T, rs, sc, alpha, beta, done, col.lo, col.hi, col.ic, col.jc,
+                              col.bc));
         __syncthreads();
         if (!done) {
             if (!__builtin_isfinite(sigma) || !__builtin_isfinite(rho)) {
@@ -851,8 +1184,9 @@ static int max_waves_s(size_t lds) {
 }
 
 static size_t ring_lds(int ring_rows, int S) {
-    // ring rows plus the zero row and the trash row of idle slots
-    return (size_t)(ring_rows + 2) * S * sizeof(double);
+    // ring rows plus the zero row and the trash row of idle slots, then the
+    // entry staging area (16-byte aligned)
+    return (((size_t)(ring_rows + 2) * S * sizeof(double) + 15) & ~(size_t)15) + (size_t)kStageChunks * 16;
 }
 
 int pcg_max_waves(int S, int ring_rows) {

@@ -338,7 +338,7 @@ def test_grid2k_all_outages_batched(gp, grids, block, tol):
 
 def test_grid10k_all_outages(gp, grids):
     """Every outage of the 10,000-bus grid in the benchmark's launch: the
-    library's own row order, assembly and ILU(0), block 4, a 64-row
+    library's own row order, assembly and ILU(0), block 16, a 64-row
     look-ahead window, stop 1e-12, solved twice (the second solve ranks its
     queue by the first one's iterations, as the timed solves do).  Angles,
     flows, island flags, statuses and true residuals of all 13,500 outages
@@ -348,7 +348,7 @@ def test_grid10k_all_outages(gp, grids):
     matrix."""
     g = grids["grid10k"]
     thb, A = oracle.base_case(g)
-    ctx = _ctx(gp, g, block=4, perm="rcm", lookahead=64)
+    ctx = _ctx(gp, g, block=16, perm="rcm", lookahead=64)
     assert np.abs(ctx.base()[1] - thb).max() <= 1e-9
     outs = np.arange(g.m)
     first = _run(gp, ctx, g, outs, tol=1e-12)
