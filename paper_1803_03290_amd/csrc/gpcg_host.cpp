@@ -410,7 +410,7 @@ struct CsrH {
 struct HostProg {
     int steps = 0, ring = 1;
     std::vector<int32_t> rec;  // 4 per (step, slot)
-    std::vector<int32_t> ent;  // 3 per (step, entry, slot), chunk-major (see gpcg::Program)
+    std::vector<int32_t> ent;  // 3 per (step, entry, slot), chunk-major (see gpcg::Program); staged: blocks
 };
 
 // One slot of a step before packing.
@@ -548,6 +548,20 @@ HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, boo
         for (int c = 0; c < 3 * K / 4; ++c)
             for (int k = 0; k < R; ++k)
                 for (int t = 0; t < 4; ++t) H.ent.push_back(w[(size_t)k * 3 * K + c * 4 + t]);
+    }
+    if (gpcg::staged(S, K)) {
+        // staged blocks: step s's entry chunks, then the records of step
+        // s + ahead (the last, idle, padding step's past the end)
+        const size_t n = all.size(), ent_step = (size_t)R * 3 * K, rec_step = (size_t)R * 4;
+        const size_t ahead = (size_t)gpcg::stage_rec_ahead(tri);
+        std::vector<int32_t> blocks;
+        blocks.reserve(n * (ent_step + rec_step));
+        for (size_t st_i = 0; st_i < n; ++st_i) {
+            blocks.insert(blocks.end(), H.ent.begin() + st_i * ent_step, H.ent.begin() + (st_i + 1) * ent_step);
+            const size_t r = std::min(st_i + ahead, n - 1);
+            blocks.insert(blocks.end(), H.rec.begin() + r * rec_step, H.rec.begin() + (r + 1) * rec_step);
+        }
+        H.ent.swap(blocks);
     }
     return H;
 }

@@ -35,6 +35,27 @@ constexpr int kPadSteps = 32;  // idle steps appended to every program (>= the d
 constexpr int kEntTri = 4;
 constexpr int kEntProd = 8;
 
+// Prefetch depths of the sweeps: vector rows are loaded D steps ahead of
+// their step (triangular solves, product).
+constexpr int kPrefetchTri = 8;
+constexpr int kPrefetchProd = 6;
+
+// Staged programs (blocks of 4 scenarios or more).  A step's entry chunks
+// and, behind them, the R row records of a later step form one block of
+// 16-byte chunks that a wave loads once, one chunk per lane, and hands to
+// its lanes through a per-wave LDS staging area.  The entries are read from
+// there kStageLook steps before their step runs; the records ride
+// stage_rec_ahead() steps ahead of the block's own step, so that each
+// record arrives one step before its vector rows are loaded.
+constexpr int kStageChunks = 2 * kWave;  // chunks of a wave's staging area
+constexpr int kStageLookTri = 3;
+constexpr int kStageLookProd = 2;
+constexpr int stage_chunks(int S, int K) { return (3 * K / 4 + 1) * (kWave / S); }
+constexpr bool staged(int S, int K) { return stage_chunks(S, K) <= kStageChunks; }
+constexpr int stage_rec_ahead(bool tri) {
+    return tri ? kPrefetchTri + 2 - kStageLookTri : kPrefetchProd + 1 - kStageLookProd;
+}
+
 // A sweep program: the steps one wavefront walks, R row slots per step, each
 // slot with a fixed number K of packed matrix entries (padding entries carry
 // value 0 and point at the ring's zero row).

@@ -146,18 +146,19 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
 }
 
 // ---- staged entries --------------------------------------------------------
-// A step's NC = C R entry chunks, loaded once each: load i of lane l takes
-// chunk (i kWave + l) mod NC, so NL loads cover the step (lanes past NC
-// repeat chunks of the same step and write them to unused staging rows).
+// A block of NB chunks (a step's NC = C R entry chunks, then R row records of
+// a later step), loaded once each: load i of lane l takes chunk
+// (i kWave + l) mod NB, so NL loads cover the block (lanes past NB repeat
+// chunks of the same block and write them to unused staging rows).
 // The staging area holds NL kWave chunks; a wave writes it and reads it back
 // in program order, and its LDS instructions complete in order, so one area
 // per wave serves every step.
-constexpr int kStageChunks = 2 * kWave;  // 16-byte chunks of a wave's staging area
-
 template <int S, int K>
 struct Stage {
-    static constexpr int R = kWave / S, C = 3 * K / 4, NC = C * R, NL = (NC + kWave - 1) / kWave;
-    static constexpr bool kOn = NL * kWave <= kStageChunks;
+    static constexpr int R = kWave / S, C = 3 * K / 4, NC = C * R;  // entry chunks of a step
+    static constexpr int NB = stage_chunks(S, K);                    // block: entries, then R records
+    static constexpr int NL = (NB + kWave - 1) / kWave;
+    static constexpr bool kOn = staged(S, K);
 };
 
 // the chunks of a step lane l loads: i kWave + l, wrapped into the step
@@ -166,7 +167,7 @@ struct StageLane {
     int j[Stage<S, K>::NL];
     __device__ __forceinline__ explicit StageLane(int lane) {
 #pragma unroll
-        for (int i = 0; i < Stage<S, K>::NL; ++i) j[i] = (i * kWave + lane) % Stage<S, K>::NC;
+        for (int i = 0; i < Stage<S, K>::NL; ++i) j[i] = (i * kWave + lane) % Stage<S, K>::NB;
     }
 };
 
@@ -376,11 +377,13 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
                                                    int rs, int sc, double alpha) {
     constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
     using St = Stage<S, K>;
-    constexpr int R = St::R, NC = St::NC, NL = St::NL;
-    constexpr int NE = 4, LA = 3;  // entry register slots; entries read from LDS LA steps ahead of use
+    constexpr int R = St::R, NC = St::NC, NB = St::NB, NL = St::NL;
+    constexpr int NE = 4, LA = kStageLookTri;  // entry register slots; entries read from LDS LA steps ahead of use
     static_assert(H % EQ == 0 && H % NE == 0 && EQ >= 1, "entry slots must tile the unrolled loop");
     static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
                   "prefetch past the last step must stay in the padding");
+    static_assert(D == kPrefetchTri && LA + stage_rec_ahead(true) == D + 2 && D + 3 <= H,
+                  "a block's records are those of step d + D + 2, read at step d (host packing)");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
@@ -392,19 +395,19 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
     ivec4 q[EQ][NL];   // raw chunks of steps LA .. LA + EQ - 1 ahead
     Ents<K> eq[NE];    // entries of steps d .. d + LA
     const int4 *hb0 = head_slot<S>(g, z0, rs);
-    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+    const int4 *qb0 = g.ent + (size_t)z0 * NB;
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+    for (int d = 0; d < D + 2; ++d) hq[d] = hb0[d * R];  // later records arrive with the staged blocks
 #pragma unroll
     for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_load<S, K>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -414,8 +417,7 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
     fwd_vec<S>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
-        const int4 *hb = head_slot<S>(g, sb, rs);
-        const int4 *qb = g.ent + (size_t)sb * NC;
+        const int4 *qb = g.ent + (size_t)sb * NB;
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int4 h = hq[d];
@@ -442,9 +444,9 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
             // step d - 1 used; then the raw slot takes step d + LA + EQ
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
+            hq[(d + D + 2) % H] = stage[NC + rs];  // the record of step (d + D + 2)
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
             fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -549,11 +551,13 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
                                                    int rs, int sc, int lo, int hi) {
     constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
     using St = Stage<S, K>;
-    constexpr int R = St::R, NC = St::NC, NL = St::NL;
-    constexpr int NE = 4, LA = 3;
+    constexpr int R = St::R, NC = St::NC, NB = St::NB, NL = St::NL;
+    constexpr int NE = 4, LA = kStageLookTri;
     static_assert(H % EQ == 0 && H % NE == 0 && EQ >= 1, "entry slots must tile the unrolled loop");
     static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
                   "prefetch past the last step must stay in the padding");
+    static_assert(D == kPrefetchTri && LA + stage_rec_ahead(true) == D + 2 && D + 3 <= H,
+                  "a block's records are those of step d + D + 2, read at step d (host packing)");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
@@ -565,19 +569,19 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     ivec4 q[EQ][NL];
     Ents<K> eq[NE];
     const int4 *hb0 = head_slot<S>(g, z0, rs);
-    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+    const int4 *qb0 = g.ent + (size_t)z0 * NB;
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+    for (int d = 0; d < D + 2; ++d) hq[d] = hb0[d * R];  // later records arrive with the staged blocks
 #pragma unroll
     for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_load<S, K>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -586,8 +590,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     bwd_vec<S>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);
-        const int4 *hb = head_slot<S>(g, sb, rs);
-        const int4 *qb = g.ent + (size_t)sb * NC;
+        const int4 *qb = g.ent + (size_t)sb * NB;
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int4 h = hq[d];
@@ -612,9 +615,9 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
             }
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
+            hq[(d + D + 2) % H] = stage[NC + rs];  // the record of step (d + D + 2)
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
             bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -716,16 +719,17 @@ __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ri
 
 template <int S, int D>
 __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
-                                                    int rs, int sc,
-                                             double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
-                                             double bc) {
+                                                    int rs, int sc, double alpha, double beta, bool done, int lo,
+                                                    int hi, int ic, int jc, double bc) {
     constexpr int H = 2 * D, K = kEntProd;
     using St = Stage<S, K>;
-    constexpr int R = St::R, NC = St::NC, NL = St::NL;
-    constexpr int NE = 2, LA = 2, EQ = 2;  // entry slots, LDS read-ahead, raw-load distance
+    constexpr int R = St::R, NC = St::NC, NB = St::NB, NL = St::NL;
+    constexpr int NE = 2, LA = kStageLookProd, EQ = 2;  // entry slots, LDS read-ahead, raw-load distance
     static_assert(H % EQ == 0 && H % NE == 0, "entry slots must tile the unrolled loop");
     static_assert(2 * H - 1 <= kPadSteps && H - 1 + LA + EQ + 1 <= kPadSteps,
                   "prefetch past the last step must stay in the padding");
+    static_assert(D == kPrefetchProd && LA + stage_rec_ahead(false) == D + 1 && D + 2 <= H,
+                  "a block's records are those of step d + D + 1, read at step d (host packing)");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
@@ -742,23 +746,22 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
     ivec4 q[EQ][NL];
     Ents<K> eq[NE];
     const int4 *hb0 = head_slot<S>(g, z0, rs);
-    const int4 *qb0 = g.ent + (size_t)z0 * NC;
+    const int4 *qb0 = g.ent + (size_t)z0 * NB;
 #pragma unroll
-    for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
+    for (int d = 0; d < D + 1; ++d) hq[d] = hb0[d * R];  // later records arrive with the staged blocks
 #pragma unroll
     for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NC, L);
+        raw_load<S, K>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NC, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
-        const int4 *hb = head_slot<S>(g, sb, rs);
-        const int4 *qb = g.ent + (size_t)sb * NC;
+        const int4 *qb = g.ent + (size_t)sb * NB;
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int4 h = hq[d];
@@ -777,8 +780,9 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
             // step's gather has read; the raw slot takes step d + LA + EQ
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NC, L);
-            hq[d] = hb[(d + H) * R];
+            hq[(d + D + 1) % H] = stage[NC + rs];  // the record of step (d + D + 1)
+            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
+
             {
                 xp_put(T, lo_, v.x + alpha * v.p, pn);
                 const double dot = gdot(G);
@@ -1141,12 +1145,10 @@ __global__ void queue_reset_kernel(const PcgParams *grids, int n_grids, int32_t 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-constexpr int kPrefetch = 8;      // steps of prefetch in the triangular sweeps
-constexpr int kPrefetchProd = 6;  // steps of prefetch in the product sweep
 
 template <int S>
 static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, hipStream_t st) {
-    auto kern = pcg_wave_kernel<S, kPrefetch, kPrefetchProd>;
+    auto kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1159,7 +1161,7 @@ static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, h
 
 template <int S>
 static hipError_t launch_multi_s(const PcgParams *grids, int n_grids, int n_waves, size_t lds, hipStream_t st) {
-    auto kern = pcg_multi_kernel<S, kPrefetch, kPrefetchProd>;
+    auto kern = pcg_multi_kernel<S, kPrefetchTri, kPrefetchProd>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1175,7 +1177,7 @@ static int max_waves_s(size_t lds) {
     int per_cu = 0, cu = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    auto kern = pcg_wave_kernel<S, kPrefetch, kPrefetchProd>;
+    auto kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd>;
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
