@@ -337,8 +337,8 @@ UNEVEN = ("uneven500", "uneven1000", "uneven2000", "uneven3000", "uneven5000", "
           "uneven20000")
 
 
-BATCH_SHAPES = ((4, 0), (8, 0), (16, 0), (8, 64), (8, 1024))
-BATCH_DEFAULT_SHAPE = (8, 0)  # the autotuner's pick over BATCH_SHAPES on the uneven workload
+BATCH_SHAPES = ((4, 0), (8, 0), (8, 64), (16, 0), (16, 64))
+BATCH_DEFAULT_SHAPE = (8, 64)  # the autotuner's pick over BATCH_SHAPES on the uneven workload
 
 
 def batch_measure(gp, torch, tol: float, max_iter: int, reps: int = 2, names=UNEVEN, shapes=BATCH_SHAPES):
