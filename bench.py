@@ -240,7 +240,7 @@ def adjoint_measure(gp, torch, grid, S: int = 16, reps: int = 2, tol: float = 1e
             "all_converged": bool(np.all(st <= 5))}
 
 
-def fdpf_measure(gp, torch, grid, S: int = 8, scale: float = 1e-4, n_outer: int = 3, tol: float = 1e-12,
+def fdpf_measure(gp, torch, grid, S: int = 16, scale: float = 1e-4, n_outer: int = 3, tol: float = 1e-12,
                  reps: int = 1):
     """The power-flow workload: n_outer fast-decoupled iterations (a B' and a
     B'' batched solve each) for every outage, from the base state, timed with
@@ -423,7 +423,7 @@ def main():
     ap.add_argument("--spmm-only", action="store_true", help="only the stand-alone product measurement")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-workload", default="grid10k", help="grid of the overload-gradient measurement")
-    ap.add_argument("--adjoint-block", type=int, default=8)
+    ap.add_argument("--adjoint-block", type=int, default=16)
     ap.add_argument("--adjoint-only", action="store_true", help="only the overload-gradient measurement")
     ap.add_argument("--no-fdpf", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")

@@ -125,8 +125,11 @@ def test_hand_grid_plain_equals_batched(gp):
 # ------------------------------------------------------- 200-bus grid
 
 
-@pytest.mark.parametrize("block", [64, 16, 4, 1])
+@pytest.mark.parametrize("block", [64, 32, 16, 8, 4, 2, 1])
 def test_grid200_all_outages(gp, grids, block):
+    """Every outage of the 200-bus grid at every block the kernel is built
+    for (blocks of 4 and more take the staged program blocks, block 2 its
+    triangular sweeps only, blocks 1 and 2 the per-lane loads elsewhere)."""
     g = grids["grid200"]
     thb, A = oracle.base_case(g)
     ctx = _ctx(gp, g, block=block)
