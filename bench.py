@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -64,8 +65,13 @@ def own_work_bytes(info: dict, scen_iters, wave_iters: int, m: int) -> float:
 
 
 def kernel_digest() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """First 16 hex digits of the SHA-256 of the PCG kernel's source with
+    comments and whitespace removed (a comment edit keeps the counters of
+    the same code valid)."""
+    with open(KERNEL_SRC, encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
 
 
 def progress(msg: str) -> None:

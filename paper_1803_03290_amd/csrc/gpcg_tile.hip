@@ -43,15 +43,18 @@ namespace {
 // is copied, no load waits on another load still in flight, and a step only
 // waits on the LDS ring that carries the dependencies between rows.
 //
-// The entries of a step serve the S column lanes of each row slot alike.
-// Where a step's entry chunks fit two loads per lane (S >= 4), each chunk is
-// loaded once: lane l loads chunk l of the step (EQ steps before it is
-// needed), writes it to a per-wave LDS staging area, and every lane reads its
-// slot's chunks back from there LA steps before the step runs.  This cuts
-// the vector-memory instructions and lane traffic of the entries by the
-// factor S (they had been the larger part of the sweeps' vector-memory
-// work); LDS, otherwise lightly used, carries the copies.  Smaller blocks
-// load each slot's chunks per lane directly.
+// The entries and the row record of a step serve the S column lanes of
+// each row slot alike.  Where a step's block (its entry chunks, then the
+// records of a later step, packed so on the host) fits two loads per lane
+// (S >= 4; the triangular sweeps at S = 2 too), each chunk is loaded once:
+// lane l loads chunk l of the block, writes it to a per-wave LDS staging
+// area, and every lane reads its slot's entries and record back from
+// there, the entries LA steps before their step and the record one step
+// before its vector rows are loaded.  This cuts the vector-memory
+// instructions and lane traffic of the program data by the factor S (they
+// had been the larger part of the sweeps' vector-memory work); LDS,
+// otherwise lightly used, carries the copies.  Smaller blocks load each
+// slot's record and entries per lane directly.
 // Vector-memory counters complete in order, so the loop has no branches
 // around loads and stores: idle slots read and write the tile's scratch row
 // (row n_r; it holds r = 0 and p = 0, and q = 0 when the forward sweep reads
