@@ -66,7 +66,8 @@ namespace {
 // pairs), and every sweep reads only the vectors it needs.  Vector bases are
 // wave-uniform (scalar registers); a step computes one 32-bit offset for all
 // of them (twice it for the pairs).
-constexpr int kEntAheadTri = 8;   // steps the triangular solves load entries ahead (staged: before the LDS copy)
+constexpr int kEntAheadTri = 8;    // steps the triangular solves load entries ahead (per-lane loads)
+constexpr int kStageAheadTri = 8;  // steps a staged block is loaded before its LDS copy (triangular solves)
 constexpr int kEntAheadProd = 2;  // steps the product loads entries ahead (direct form)
 
 // The step index as a vector register the compiler cannot see through.
@@ -378,7 +379,7 @@ __device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *rin
 template <int S, int D>
 __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
                                                    int rs, int sc, double alpha) {
-    constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
+    constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
     using St = Stage<S, K>;
     constexpr int R = St::R, NC = St::NC, NB = St::NB, NL = St::NL;
     constexpr int NE = 4, LA = kStageLookTri;  // entry register slots; entries read from LDS LA steps ahead of use
@@ -387,6 +388,7 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
                   "prefetch past the last step must stay in the padding");
     static_assert(D == kPrefetchTri && LA + stage_rec_ahead(true) == D + 2 && D + 3 <= H,
                   "a block's records are those of step d + D + 2, read at step d (host packing)");
+    static_assert(NE >= LA, "an entry slot is refilled only after its step has read it");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
@@ -552,7 +554,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
 template <int S, int D>
 __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
                                                    int rs, int sc, int lo, int hi) {
-    constexpr int H = 2 * D, EQ = kEntAheadTri, K = kEntTri;
+    constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
     using St = Stage<S, K>;
     constexpr int R = St::R, NC = St::NC, NB = St::NB, NL = St::NL;
     constexpr int NE = 4, LA = kStageLookTri;
@@ -561,6 +563,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
                   "prefetch past the last step must stay in the padding");
     static_assert(D == kPrefetchTri && LA + stage_rec_ahead(true) == D + 2 && D + 3 <= H,
                   "a block's records are those of step d + D + 2, read at step d (host packing)");
+    static_assert(NE >= LA, "an entry slot is refilled only after its step has read it");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
@@ -733,6 +736,7 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
                   "prefetch past the last step must stay in the padding");
     static_assert(D == kPrefetchProd && LA + stage_rec_ahead(false) == D + 1 && D + 2 <= H,
                   "a block's records are those of step d + D + 1, read at step d (host packing)");
+    static_assert(NE >= LA, "an entry slot is refilled only after its step has read it");
     const int lane = threadIdx.x;
     const StageLane<S, K> L(lane);
     const int z0 = opaque(0);
