@@ -149,7 +149,7 @@ __device__ __forceinline__ double gdot(const Gath<K> &G) {
     return acc;
 }
 
-// ---- staged entries --------------------------------------------------------
+// ---- staged blocks ---------------------------------------------------------
 // A block of NB chunks (a step's NC = C R entry chunks, then R row records of
 // a later step), loaded once each: load i of lane l takes chunk
 // (i kWave + l) mod NB, so NL loads cover the block (lanes past NB repeat
@@ -165,7 +165,7 @@ struct Stage {
     static constexpr bool kOn = staged(S, K);
 };
 
-// the chunks of a step lane l loads: i kWave + l, wrapped into the step
+// the chunks of a block lane l loads: i kWave + l, wrapped into the block
 template <int S, int K>
 struct StageLane {
     int j[Stage<S, K>::NL];
