@@ -378,6 +378,37 @@ def test_library_rcm_on_generated_numbering(gp, grids):
     _check_all(g, A, outs, res, gp)
 
 
+@pytest.mark.parametrize("block", [64, 16, 4, 2, 1])
+def test_hub_bus_long_rows(gp, grids, block):
+    """The 200-bus grid with one bus tied to 40 others (seeded extra
+    branches): its row of A has 44 entries and the factors' rows around it
+    run far past the entries one slot holds, so every sweep splits them
+    into continuation segments (in the staged blocks and in the per-lane
+    loads).  Every outage, in the library's own row order, against the
+    oracle's direct solve.  At block 64 the hub's bandwidth needs a larger
+    LDS window than a wavefront of 64 columns may hold: setup refuses with
+    the remedy named."""
+    g0 = grids["grid200"]
+    rng = np.random.default_rng(37)
+    hub = 57
+    have = {(min(a, b), max(a, b)) for a, b in zip(g0.br_from.tolist(), g0.br_to.tolist())}
+    extra = [b for b in rng.permutation(g0.n) if b != hub and (min(b, hub), max(b, hub)) not in have][:40]
+    f = np.r_[g0.br_from, np.minimum(extra, hub)].astype(np.int32)
+    t = np.r_[g0.br_to, np.maximum(extra, hub)].astype(np.int32)
+    x = np.r_[g0.x, rng.uniform(0.05, 0.3, len(extra))]
+    g = gridgen.Grid("grid200:hub", g0.n, f, t, x, g0.P.copy())
+    if block == 64:
+        with pytest.raises(gp.GpcgError) as e:
+            _ctx(gp, g, block=block, perm="rcm")
+        assert e.value.code == -6 and "smaller block" in str(e.value)
+        return
+    _, A = oracle.base_case(g)
+    ctx = _ctx(gp, g, block=block, perm="rcm")
+    outs = list(range(g.m))
+    res = _run(gp, ctx, g, outs)
+    _check_against_direct(g, A, outs, res)
+
+
 def test_shuffled_bus_numbering(gp, grids):
     """The 200-bus grid with buses 1..n-1 relabelled at random and the
     branch table shuffled (seeded): the library's row order, its bridge flags
