@@ -40,7 +40,8 @@ sys.path.insert(0, ROOT)
 METRIC = "N-1 scenario solves/sec to 1e-10 residual, batched vs plain PCG; HBM GB/s %"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "pcg_wave_grid10k_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1803_03290_amd", "csrc", "gpcg_tile.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1803_03290_amd", "csrc", f)
+              for f in ("gpcg_tile.hip", "gpcg_internal.h", "gpcg_device.h")]
 
 # The method's algorithmic bytes per PCG iteration of one scenario: 15 vector
 # passes of 8 bytes per row (product: read p, write q; update: read delta, p,
@@ -65,13 +66,17 @@ def own_work_bytes(info: dict, scen_iters, wave_iters: int, m: int) -> float:
 
 
 def kernel_digest() -> str:
-    """First 16 hex digits of the SHA-256 of the PCG kernel's source with
-    comments and whitespace removed (a comment edit keeps the counters of
-    the same code valid)."""
-    with open(KERNEL_SRC, encoding="utf-8") as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
-    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
+    """First 16 hex digits of the SHA-256 of the PCG kernel's sources (the
+    kernel file and the headers it is compiled with) with comments and
+    whitespace removed (a comment edit keeps the counters of the same code
+    valid)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def progress(msg: str) -> None:
