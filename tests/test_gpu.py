@@ -921,7 +921,7 @@ def test_batch_uneven_grids_against_oracle(gp, grids):
     names = ["uneven500", "uneven1000", "uneven2000", "uneven3000"]
     ctxs, outs, rhs = _batch_inputs(gp, names, grids, 8)
     tuner = gp.BlockTuner()
-    cands = ((4, 0), (8, 0), (8, 32))
+    cands = ((4, 0), (8, 32), (16, 64))
     S, look = tuner.best(ctxs, outs, rhs, candidates=cands, tol=1e-12)
     assert (S, look) in cands and tuner.best(ctxs, outs, rhs, candidates=cands, tol=1e-12) == (S, look)
     b = gp.Batch(ctxs, outs, rhs, block=S, tol=1e-12, lookahead=look)
