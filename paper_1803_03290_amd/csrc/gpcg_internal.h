@@ -72,6 +72,11 @@ constexpr int stage_rec_ahead(bool tri) {
 //     ent[(s * 3K/4 + c) * R + rs]: chunks c < K/2 hold the values of
 //     entries 2c and 2c + 1 (doubles), chunks K/2 + c' the LDS byte offsets
 //     of the ring slots (for column 0) of entries 4c' .. 4c' + 3;
+//   Staged programs (staged(S, K)) store ent as blocks of stage_chunks(S, K)
+//   chunks per step instead: the 3K/4 R entry chunks above, then the R
+//   records of step s + stage_rec_ahead(tri) (the last padding step's past
+//   the end); rec keeps every step's records for the first steps a sweep
+//   reads directly.
 //   The backward solve packs its records instead (kBwdRowBits-bit row and
 //   pre-order fields), so that 1 / U_ii rides in the same 16-byte load:
 //     rec[s * R + rs] = {row | slot << 20, pre | (aux + 1) << 20, 1 / U_ii}:
