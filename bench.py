@@ -444,7 +444,8 @@ def main():
                     help="run the uneven multi-grid batch with the autotuner's search over five tile shapes "
                          "(several minutes) instead of at the shape it picks on this workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven multi-grid batch")
-    ap.add_argument("--batch-only", action="store_true", help="only the uneven multi-grid batch")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the uneven multi-grid batch (at the tuned shape; add --batch for the search)")
     ap.add_argument("--fdpf-workload", default="grid10k", help="grid of the power-flow measurement")
     ap.add_argument("--fdpf-only", action="store_true", help="only the power-flow measurement")
     args = ap.parse_args()
@@ -499,7 +500,10 @@ def main():
         print(json.dumps(spmm_measure(gp, torch, aux_grid(args.spmm_workload), args.spmm_block)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps(batch_measure(gp, torch, args.tol, args.max_iter)), flush=True)
+        # at the tuned shape; with --batch, the tuner's whole search first
+        print(json.dumps(batch_measure(gp, torch, args.tol, args.max_iter, reps=2,
+                                       shapes=BATCH_SHAPES if args.batch else (BATCH_DEFAULT_SHAPE,))),
+              flush=True)
         return
     if args.fdpf_only:
         print(json.dumps(fdpf_measure(gp, torch, aux_grid(args.fdpf_workload))), flush=True)
