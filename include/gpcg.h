@@ -109,6 +109,9 @@ typedef struct {
     int32_t n_bridges;
     int32_t base_iters; /* PCG iterations spent on the base-case solve (all refinement steps) */
     double base_resid;  /* relative residual of the base-case state, double-double */
+    int32_t sym_factors; /* 1: U = diag(U) L^T to 1e-12 (M = L U symmetric, as for the ILU(0) of
+                            A and the Jacobi pair): r'z is formed as y' D^-1 y in the forward
+                            sweep; 0: as r'z in the backward sweep */
 } gpcg_info;
 
 /* Message describing the last error of the calling thread ("" if none). */

@@ -40,6 +40,7 @@ class Info(C.Structure):
         ("bandwidth", C.c_int32), ("block", C.c_int32), ("rows_per_step", C.c_int32),
         ("ring_fwd", C.c_int32), ("ring_bwd", C.c_int32), ("steps_fwd", C.c_int32), ("steps_bwd", C.c_int32),
         ("n_bridges", C.c_int32), ("base_iters", C.c_int32), ("base_resid", C.c_double),
+        ("sym_factors", C.c_int32),
     ]
 
     def as_dict(self):

@@ -490,6 +490,31 @@ int ring_needed(const Steps &st, const CsrH &T, bool tri, int max_ring) {
 }
 
 // Pack an expanded step list for the kernel (see gpcg::Program).
+// Whether the factors have the form U = D L^T, D = diag(U), to rounding
+// (each strictly upper U_ij within 1e-12 relative of U_ii L_ji, and the
+// other way round): then M = L U is symmetric and, with r zero on islanded
+// rows, r'z = r' (L U)^-1 r = y' D^-1 y for y = L^-1 r (Section III.A's
+// inner product, summed in the forward sweep).  The ILU(0) of a symmetric
+// matrix and the Jacobi pair have this form.
+bool factors_symmetric(const CsrH &L, const CsrH &Us, const std::vector<double> &invdiag) {
+    const int n = (int)L.rowptr.size() - 1;
+    auto at = [](const CsrH &T, int row, int col) {
+        const int32_t *b = T.col.data() + T.rowptr[row], *t = T.col.data() + T.rowptr[row + 1];
+        const int32_t *f = std::lower_bound(b, t, col);
+        return (f != t && *f == col) ? T.val[f - T.col.data()] : 0.0;
+    };
+    auto close = [](double u, double v) { return std::fabs(u - v) <= 1e-12 * std::max(std::fabs(u), std::fabs(v)); };
+    for (int i = 0; i < n; ++i)
+        for (int e = Us.rowptr[i]; e < Us.rowptr[i + 1]; ++e)  // U_ij against U_ii L_ji
+            if (!close(Us.val[e], at(L, Us.col[e], i) / invdiag[i])) return false;
+    for (int j = 0; j < n; ++j)
+        for (int e = L.rowptr[j]; e < L.rowptr[j + 1]; ++e) {  // L_ji against U_ij / U_ii
+            const int i = L.col[e];
+            if (!close(at(Us, i, j), L.val[e] / invdiag[i])) return false;
+        }
+    return true;
+}
+
 HostProg pack(const Steps &st, int R, int S, int ring, int K, const CsrH &T, bool tri,
               const std::vector<double> *invdiag, const std::vector<int32_t> &prerow) {
     HostProg H;
@@ -659,6 +684,7 @@ struct gpcg_context {
     std::vector<std::vector<int>> deps_f, deps_b;  // for schedule building
     CsrH hA, hL, hU;                               // A, L, strict upper of U
     std::vector<double> h_invdiag;
+    bool sym_factors = false;  // U = D L^T to rounding (see factors_symmetric)
     std::vector<int32_t> h_prerow;
     // sweep programs per (block, look-ahead window), shared with the batches
     // that use them
@@ -709,10 +735,10 @@ struct gpcg_context {
                 if (v >= 0) v = n_r - 1 - v;
             const Steps FS = expand(tri_steps(F.rows, R), R, gpcg::kEntTri, hL);
             const Steps BS = expand(tri_steps(B.rows, R), R, gpcg::kEntTri, hU);
-            const int wf = ring_needed(FS, hL, true, max_ring);
+            const int wf = ring_needed(FS, hL, true, std::min(max_ring, gpcg::kBwdMaxRing));
             const int wb = ring_needed(BS, hU, true, std::min(max_ring, gpcg::kBwdMaxRing));
             if (wf > 0 && wb > 0) {
-                D->f.upload(pack(FS, R, S_, wf, gpcg::kEntTri, hL, true, nullptr, h_prerow), stream);
+                D->f.upload(pack(FS, R, S_, wf, gpcg::kEntTri, hL, true, &h_invdiag, h_prerow), stream);
                 D->b.upload(pack(BS, R, S_, wb, gpcg::kEntTri, hU, true, &h_invdiag, h_prerow), stream);
                 D->p.upload(pack(P, R, S_, wp, gpcg::kEntProd, hA, false, nullptr, h_prerow), stream);
                 hip_check(hipStreamSynchronize(stream), "schedule upload");
@@ -752,6 +778,7 @@ struct gpcg_context {
         p.max_iter = max_iter;
         p.queue = queue.p;
         p.sweeps = sweeps.p;
+        p.sym = sym_factors ? 1 : 0;
         p.iters_out = iters;
         p.status_out = status;
         return p;
@@ -1511,6 +1538,7 @@ int gpcg_setup(gpcg_t *out, int32_t n_bus, int32_t m, const int32_t *br_from, co
         h->hU.col = us_col;
         h->hU.val = us_val;
         h->h_invdiag = invdiag;
+        h->sym_factors = factors_symmetric(h->hL, h->hU, invdiag);
         h->h_prerow.resize(nr);
         for (int i = 0; i < nr; ++i) h->h_prerow[i] = h->topo.pre[i + 1];
         hipStream_t st = h->stream;
@@ -1619,6 +1647,7 @@ int gpcg_get_info(gpcg_t h, gpcg_info *info) {
         I.n_bridges = h->topo.n_bridges;
         I.base_iters = h->base_iters;
         I.base_resid = h->base_resid;
+        I.sym_factors = h->sym_factors ? 1 : 0;
         *info = I;
     });
 }

@@ -72,6 +72,8 @@ constexpr int stage_rec_ahead(bool tri) {
 //     ent[(s * 3K/4 + c) * R + rs]: chunks c < K/2 hold the values of
 //     entries 2c and 2c + 1 (doubles), chunks K/2 + c' the LDS byte offsets
 //     of the ring slots (for column 0) of entries 4c' .. 4c' + 3;
+//   The forward solve's records use the backward solve's packed form too
+//   (its 1 / U_ii weights y_i^2 in r'z = y' D^-1 y).
 //   Staged programs (staged(S, K)) store ent as blocks of stage_chunks(S, K)
 //   chunks per step instead: the 3K/4 R entry chunks above, then the R
 //   records of step s + stage_rec_ahead(tri) (the last padding step's past
@@ -122,6 +124,10 @@ struct PcgParams {
     const double *rhs_cols;
     int rhs_ld;
     int zero_start;  // 1: start from x = 0 (r0 = P'_M), the result is theta itself
+    // 1: the factors have the form U = D L^T (M = L U symmetric), so r'z is
+    // summed in the forward sweep as y' D^-1 y and the backward sweep does not
+    // read r; 0: r'z in the backward sweep
+    int sym;
     // scenarios: queue position j takes scenario order[n_out - 1 - j] (the
     // order sorted by expected work, taken from its heavy end; NULL: j)
     const int32_t *outages;

@@ -298,21 +298,23 @@ __device__ __forceinline__ double tree_dot(const double (&r)[K], const Ents<K> &
     return acc[0];
 }
 
-// ---- forward: r -= alpha q, ||r||^2, y = L^-1 r ---------------------------
+// ---- forward: r -= alpha q, ||r||^2, y = L^-1 r, y' D^-1 y -----------------
+// Its records are packed like the backward solve's, so that 1 / U_ii rides
+// in them: with factors U = D L^T, y' D^-1 y = r' (L U)^-1 r = r'z.
 struct FwdVec {
     double r, q;
 };
 
 template <int S>
 __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
-    const unsigned o = sweep_off<S>(T, h.x, sc);
+    const unsigned o = sweep_off<S>(T, h.x & kBwdRowMask, sc);  // packed record (see the backward solve)
     const dvec2 rq = ry_get(T, o);  // r and q (q sits where y and z were)
     v.r = rq.x;
     v.q = rq.y;
 }
 
 template <int S, int D>
-__device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+__device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                                    double alpha) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
@@ -321,7 +323,7 @@ __device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *rin
     const int z0 = opaque(0);
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
-    double rr = 0.0, carry = 0.0;
+    double rr = 0.0, carry = 0.0, rho = 0.0;
     int4 hq[H];
     FwdVec vq[D];
     Ents<K> eq[E];
@@ -346,22 +348,23 @@ __device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *rin
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int4 h = hq[d];
-            asm volatile("" ::"v"(h.z));  // unused here; keeps the record one 16-byte load
             // A
             const double dot = tree_dot(G, eq[d % E]);
             const double y = rc - dot;
-            ring_put(ring, h.y + lane_off, y);
+            ring_put(ring, (int)(((unsigned)h.x >> kBwdRowBits) * (S * 8)) + lane_off, y);
             ring_addr(ga, eq[(d + 1) % E], lane_off);
             ring_read(G, ga, ring);
             __builtin_amdgcn_sched_barrier(0);
             // B
             {
-                const unsigned o = sweep_off<S>(T, h.x, sc);
-                const bool cont = h.w == 1;
+                const unsigned o = sweep_off<S>(T, h.x & kBwdRowMask, sc);
+                const bool cont = ((unsigned)h.y >> kBwdRowBits) == 2u;
                 // a continuation's partial y is not stored: the scratch row's
                 // w is read back as q by later idle slots of this sweep
                 ry_put(T, o, r, cont ? 0.0 : y);
-                rr = __builtin_fma(r, r, rr);  // idle slots hold the scratch row's r = 0
+                rr = __builtin_fma(r, r, rr);
+                // y' D^-1 y: 1 / U_ii is 0 for idle and continuation slots
+                rho = __builtin_fma(y * __hiloint2double(h.w, h.z), y, rho);  // idle slots hold the scratch row's r = 0
                 carry = cont ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
                 r = v.r - alpha * v.q;
@@ -373,11 +376,14 @@ __device__ __forceinline__ double fwd_sweep_direct(const Program &g, double *rin
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    return rr;
+    dvec2 out;
+    out.x = rr;
+    out.y = rho;
+    return out;
 }
 
 template <int S, int D>
-__device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+__device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
                                                    int rs, int sc, double alpha) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
     using St = Stage<S, K>;
@@ -394,7 +400,7 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
     const int z0 = opaque(0);
     const int lane_off = sc * 8;
     if (rs == 0) ring_put(ring, g.ring * S * 8 + lane_off, 0.0);
-    double rr = 0.0, carry = 0.0;
+    double rr = 0.0, carry = 0.0, rho = 0.0;
     int4 hq[H];
     FwdVec vq[D];
     ivec4 q[EQ][NL];   // raw chunks of steps LA .. LA + EQ - 1 ahead
@@ -426,20 +432,21 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
 #pragma unroll
         for (int d = 0; d < H; ++d) {
             const int4 h = hq[d];
-            asm volatile("" ::"v"(h.z));  // unused here; keeps the record one 16-byte load
             // A
             const double dot = tree_dot(G, eq[d % NE]);
             const double y = rc - dot;
-            ring_put(ring, h.y + lane_off, y);
+            ring_put(ring, (int)(((unsigned)h.x >> kBwdRowBits) * (S * 8)) + lane_off, y);
             ring_addr(ga, eq[(d + 1) % NE], lane_off);
             ring_read(G, ga, ring);
             __builtin_amdgcn_sched_barrier(0);
             // B
             {
-                const unsigned o = sweep_off<S>(T, h.x, sc);
-                const bool cont = h.w == 1;
+                const unsigned o = sweep_off<S>(T, h.x & kBwdRowMask, sc);
+                const bool cont = ((unsigned)h.y >> kBwdRowBits) == 2u;
                 ry_put(T, o, r, cont ? 0.0 : y);
                 rr = __builtin_fma(r, r, rr);
+                // y' D^-1 y: 1 / U_ii is 0 for idle and continuation slots
+                rho = __builtin_fma(y * __hiloint2double(h.w, h.z), y, rho);
                 carry = cont ? carry + dot : 0.0;
                 const FwdVec v = vq[(d + 1) % D];
                 r = v.r - alpha * v.q;
@@ -455,12 +462,16 @@ __device__ __forceinline__ double fwd_sweep_staged(const Program &g, double *rin
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    return rr;
+    dvec2 out;
+    out.x = rr;
+    out.y = rho;
+    return out;
 }
 
+// returns {||r||^2, y' D^-1 y} of this lane's rows
 template <int S, int D>
-__device__ __forceinline__ double fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
-                                            int sc, double alpha) {
+__device__ __forceinline__ dvec2 fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+                                           int sc, double alpha) {
     if constexpr (Stage<S, kEntTri>::kOn)
         return fwd_sweep_staged<S, D>(g, ring, stage, T, rs, sc, alpha);
     else
@@ -482,14 +493,20 @@ struct BwdVec {
     double y, r;
 };
 
-template <int S>
+// RZ: the sweep forms r'z (reads r); else only y
+template <int S, bool RZ>
 __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile &T, int sc) {
     const unsigned o = sweep_off<S>(T, bwd_row(h), sc);
-    const dvec2 ry = ry_get(T, o);
-    v.y = ry.y;
-    v.r = ry.x;
+    if constexpr (RZ) {
+        const dvec2 ry = ry_get(T, o);
+        v.y = ry.y;
+        v.r = ry.x;
+    } else {
+        v.y = y_get(T, o);
+        v.r = 0.0;
+    }
 }
-template <int S, int D>
+template <int S, int D, bool RZ>
 __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
                                                    int lo, int hi) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
@@ -507,7 +524,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
 #pragma unroll
     for (int d = 0; d < H; ++d) hq[d] = hb0[d * R];
 #pragma unroll
-    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], T, sc);
+    for (int d = 0; d < D; ++d) bwd_vec<S, RZ>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
@@ -515,7 +532,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
     ring_addr(ga, eq[0], lane_off);
     ring_read(G, ga, ring);
     double yc = vq[0].y, dv = bwd_dinv(hq[0]), r = vq[0].r;  // step 0's row
-    bwd_vec<S>(vq[0], hq[D], T, sc);
+    bwd_vec<S, RZ>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
         const int4 *hb = head_slot<S>(g, sb, rs);
@@ -543,7 +560,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
                 r = v.r;
             }
             load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
-            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            bwd_vec<S, RZ>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
             hq[d] = hb[(d + H) * R];
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -551,7 +568,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
     return rz;
 }
 
-template <int S, int D>
+template <int S, int D, bool RZ>
 __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
                                                    int rs, int sc, int lo, int hi) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
@@ -579,7 +596,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
 #pragma unroll
     for (int d = 0; d < D + 2; ++d) hq[d] = hb0[d * R];  // later records arrive with the staged blocks
 #pragma unroll
-    for (int d = 0; d < D; ++d) bwd_vec<S>(vq[d], hq[d], T, sc);
+    for (int d = 0; d < D; ++d) bwd_vec<S, RZ>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
         raw_load<S, K>(q[0], qb0 + d * NB, L);
@@ -593,7 +610,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     ring_addr(ga, eq[0], lane_off);
     ring_read(G, ga, ring);
     double yc = vq[0].y, dv = bwd_dinv(hq[0]), r = vq[0].r;  // step 0's row
-    bwd_vec<S>(vq[0], hq[D], T, sc);
+    bwd_vec<S, RZ>(vq[0], hq[D], T, sc);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);
         const int4 *qb = g.ent + (size_t)sb * NB;
@@ -623,20 +640,20 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
             hq[(d + D + 2) % H] = stage[NC + rs];  // the record of step (d + D + 2)
             raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
-            bwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
+            bwd_vec<S, RZ>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
     return rz;
 }
 
-template <int S, int D>
+template <int S, int D, bool RZ>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
                                             int sc, int lo, int hi) {
     if constexpr (Stage<S, kEntTri>::kOn)
-        return bwd_sweep_staged<S, D>(g, ring, stage, T, rs, sc, lo, hi);
+        return bwd_sweep_staged<S, D, RZ>(g, ring, stage, T, rs, sc, lo, hi);
     else
-        return bwd_sweep_direct<S, D>(g, ring, T, rs, sc, lo, hi);
+        return bwd_sweep_direct<S, D, RZ>(g, ring, T, rs, sc, lo, hi);
 }
 
 // ---- product: on the look-ahead row delta += alpha p_old and p = z + beta
@@ -1051,7 +1068,8 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
         __syncthreads();
         ++sweeps;
         // ---- forward sweep: r -= alpha q, y = L^-1 r ----------------------
-        double rrp = fwd_sweep<S, D>(p.fwd, ring, stage, T, rs, sc, alpha);
+        const dvec2 fr = fwd_sweep<S, D>(p.fwd, ring, stage, T, rs, sc, alpha);
+        double rrp = fr.x;
         __syncthreads();
         rrp = col_sum<S>(rrp);
         if (col.scen >= 0 && !done) {
@@ -1079,7 +1097,13 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
         }
 
         // ---- backward sweep: z = P_M U^-1 y, rho = r'z ---------------------
-        const double rz = col_sum<S>(bwd_sweep<S, D>(p.bwd, ring, stage, T, rs, sc, col.lo, col.hi));
+        double rz;
+        if (p.sym) {  // r'z = y' D^-1 y from the forward sweep
+            (void)bwd_sweep<S, D, false>(p.bwd, ring, stage, T, rs, sc, col.lo, col.hi);
+            rz = col_sum<S>(fr.y);
+        } else {
+            rz = col_sum<S>(bwd_sweep<S, D, true>(p.bwd, ring, stage, T, rs, sc, col.lo, col.hi));
+        }
         __syncthreads();
         const double beta = (col.k == 0 || done) ? 0.0 : rz / rho;
         rho = rz;

@@ -210,6 +210,32 @@ def test_exact_factors_converge_in_one_step(gp, grids):
 
 
 @pytest.mark.parametrize("block", [16, 1])
+def test_factor_form_selects_the_inner_product(gp, grids, block):
+    """Section III.A's r'z.  The library's ILU(0) has the form
+    U = diag(U) L^T, so the forward sweep forms r'z as y' D^-1 y
+    (sym_factors = 1); the same factors with U's strict upper part scaled by
+    1 + 1e-9 do not (sym_factors = 0: r'z in the backward sweep).  Both
+    solve every outage of the 200-bus grid to the oracle's angles.  (Their
+    iteration counts differ: the perturbed preconditioner is no longer
+    symmetric, which costs CG iterations; the library's own factors are
+    checked against the textbook PCG's counts elsewhere.)"""
+    g = grids["grid200"]
+    perm = gridgen.rcm_perm(g)
+    A = gp.assemble(g.n, g.br_from, g.br_to, g.x, perm=perm)
+    L, U = gp.ilu0(A)
+    rows = np.repeat(np.arange(U.n), np.diff(U.rowptr))
+    U2 = gp.binding.Csr(U.rowptr, U.col, np.where(U.col > rows, U.val * (1 + 1e-9), U.val))
+    _, Ao = oracle.base_case(g)
+    outs = list(range(g.m))
+    for UU, flag in ((U, 1), (U2, 0)):
+        ctx = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=block, perm=perm, A=A, L=L, U=UU)
+        assert ctx.info()["sym_factors"] == flag
+        _check_against_direct(g, Ao, outs, _run(gp, ctx, g, outs))
+    jac = gp.Context(g.n, g.br_from, g.br_to, g.x, g.P, block=block, perm=perm, precond="jacobi")
+    assert jac.info()["sym_factors"] == 1
+
+
+@pytest.mark.parametrize("block", [16, 1])
 def test_breakdown_status_on_a_negative_definite_operator(gp, grids, block):
     """A sign-flipped operator (A = -B', factors of +B', base state 0): the
     first p'Ap is negative, so every scenario stops with BREAKDOWN after no
