@@ -1034,8 +1034,9 @@ __device__ __forceinline__ void refill(const PcgParams &p, const Tile &T, int rs
 // The PCG of every scenario this wave takes (Section III.A), in correction
 // form from the base state (Section III.B), with the base-case ILU(0)
 // preconditioner (Section IV.B).  Per iteration: forward sweep (r -= alpha q,
-// ||r||^2, y = L^-1 r), stop test, backward sweep (z = P_M U^-1 y, r'z),
-// beta, product sweep (delta += alpha p_old, p = z + beta p, q = A_c p with
+// ||r||^2, y = L^-1 r, and r'z = y' D^-1 y when the factors have the form
+// U = D L^T), stop test, backward sweep (z = P_M U^-1 y; r'z here for other
+// factors), beta, product sweep (delta += alpha p_old, p = z + beta p, q = A_c p with
 // the outaged branch shielded, p'q), alpha.  Returns the iterations the wave
 // ran (sweeps of its columns, counting stopped ones).
 template <int S, int D, int DP>
