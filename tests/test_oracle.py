@@ -291,6 +291,33 @@ def test_ilu0_defining_property(grids):
     assert np.all(U.diagonal() > 0)
 
 
+def test_inner_product_from_the_forward_solve(grids):
+    """Reading of Section III.A's r'z for factors U = D L^T: with r zero on
+    an outage's islanded rows and z = P_M (L U)^-1 r, r'z equals y' D^-1 y
+    for y = L^-1 r (the masking drops out because r_I = 0).  Checked with
+    the oracle's ILU(0) of B' on an islanding outage of the 2k grid, for
+    seeded r; and the identity fails for a planted nonsymmetric U (the
+    strict upper part scaled), which is why the device checks the form."""
+    import scipy.sparse.linalg as spla
+
+    g = grids["grid2k"]
+    _, A = oracle.base_case(g)
+    L, U = oracle.ilu0(A)
+    n = A.shape[0]
+    Lu = (L + sp.eye(n)).tocsr()
+    c = next(k for k in range(g.m) if oracle.is_bridge(g, k) and oracle.island_of(g, k).sum() > 3)
+    main = ~oracle.island_of(g, c)[1:]
+    rng = np.random.default_rng(43)
+    d = U.diagonal()
+    for Uc, same in ((U, True), (sp.triu(U, 1) * (1 + 1e-6) + sp.diags(d), False)):
+        for _ in range(3):
+            r = rng.normal(size=n) * main
+            y = spla.spsolve_triangular(Lu, r, lower=True)
+            z = spla.spsolve_triangular(Uc.tocsr(), y, lower=False) * main
+            rz, yy = float(r @ z), float(y @ (y / d))
+            assert (abs(rz - yy) <= 1e-11 * abs(rz)) == same, (rz, yy)
+
+
 def test_ilu0_exact_on_tree():
     """With no fill possible (a tree eliminated leaves first), ILU(0) is the
     exact LU."""
