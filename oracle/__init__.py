@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE.  This package is the plain, slow, obviously-correct
 reference that the device library is checked against.  Only the tests, the
-``smoke()`` entry of the build driver and the CPU-baseline leg of the
+``smoke()`` entry point of ``__graft_entry__.py`` and the CPU-baseline leg of the
 benchmark may import it.  The device library never calls it and shares no code
 with it: the only common input is the seeded grid drawn by ``gridgen``.
 
