@@ -241,10 +241,13 @@ struct FdpfParams {
 // return hipSuccess or the launch error.
 // n_waves persistent wavefronts (each with a workspace slot) over one queue;
 // the queue and sweep counters are reset by a kernel launched first.
-hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, hipStream_t st);
+// stream: the sweeps' vector accesses carry the non-temporal hint (for a
+// queue ranked by an iteration record, where few columns idle; S > 1).
+hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, bool stream, hipStream_t st);
 // several grids in one launch: grids (device, n_grids entries, heaviest
 // first) share the workspace slots; ring_rows = the largest ring of any grid
-hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, hipStream_t st);
+hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, bool stream,
+                            hipStream_t st);
 // wavefronts of the PCG kernel at block S that fit the device at once
 int pcg_max_waves(int S, int ring_rows);
 hipError_t launch_outputs(const OutParams &prm, hipStream_t st);

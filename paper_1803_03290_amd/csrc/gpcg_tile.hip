@@ -28,6 +28,7 @@
 // overwritten.
 #include "gpcg_device.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace gpcg {
@@ -198,7 +199,9 @@ __device__ __forceinline__ void stage_read(Ents<K> &E, const int4 *stage, int rs
 }
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
-// the {delta, p} pairs at xp, r, and w (y, then z, then q).
+// the {delta, p} pairs at xp, r, and w (y, then z, then q).  NT selects the
+// cache policy of the sweeps' vector accesses (below).
+template <bool NT>
 struct Tile {
     double *xp, *r, *w;
     double *v[kVectors];
@@ -208,50 +211,82 @@ struct Tile {
 
 // byte offset of (row, column sc) inside any vector of a tile (idle slots
 // name the scratch row n_r)
-template <int S>
-__device__ __forceinline__ unsigned row_off(const Tile &T, int row, int sc) {
+template <int S, bool NT>
+__device__ __forceinline__ unsigned row_off(const Tile<NT> &T, int row, int sc) {
     return ((unsigned)row * S + sc) * 8u;
 }
 
 // the same inside the sweeps: a column without a scenario reads and writes
 // its scratch row only (one cache line, so the finished columns of a wave
 // cost no memory traffic while the others finish)
-template <int S>
-__device__ __forceinline__ unsigned sweep_off(const Tile &T, int row, int sc) {
+template <int S, bool NT>
+__device__ __forceinline__ unsigned sweep_off(const Tile<NT> &T, int row, int sc) {
     return ((unsigned)(T.idle ? T.nr : row) * S + sc) * 8u;
 }
 
-// the pair {delta, p} at the element offset off of the other vectors
-__device__ __forceinline__ dvec2 xp_get(const Tile &T, unsigned off) {
-    return *(const dvec2 *)((const char *)T.xp + 2 * off);
+// Cache policy of the vector accesses.  A row of a vector is next touched
+// one sweep later, after the wave has streamed through the whole vector and
+// the other waves through theirs; where that is more than the Infinity
+// Cache holds (4.3 GB on the 10,000-bus grid at block 16) no cache keeps
+// it, and with NT the accesses carry the non-temporal (streaming) hint,
+// which leaves L2 to the matrix and factor entries that every wave reads
+// (there: 0.47 TB less read traffic per launch and 3.7 % faster; the hint
+// on loads or on stores alone made no difference).  The hint also streams
+// the scratch row that idle columns write at every step, so it pays only
+// while few columns idle.  The host takes it when the vectors exceed the
+// Infinity Cache and the queue is ranked by an iteration record (idle
+// overhead near 1.0), the ordinary policy otherwise (the first solve,
+// ranked by the analytic key, sweeps about 1.3 times the busy columns and
+// took 1.91 s instead of 1.57 s with the hint).
+template <bool NT, class V>
+__device__ __forceinline__ V vload(const V *a) {
+    if constexpr (NT) return __builtin_nontemporal_load(a);
+    else return *a;
 }
 
-__device__ __forceinline__ void xp_put(const Tile &T, unsigned off, double x, double pv) {
+template <bool NT, class V>
+__device__ __forceinline__ void vstore(V v, V *a) {
+    if constexpr (NT) __builtin_nontemporal_store(v, a);
+    else *a = v;
+}
+
+// the pair {delta, p} at the element offset off of the other vectors
+template <bool NT>
+__device__ __forceinline__ dvec2 xp_get(const Tile<NT> &T, unsigned off) {
+    return vload<NT>((const dvec2 *)((const char *)T.xp + 2 * off));
+}
+
+template <bool NT>
+__device__ __forceinline__ void xp_put(const Tile<NT> &T, unsigned off, double x, double pv) {
     dvec2 w;
     w.x = x;
     w.y = pv;
-    *(dvec2 *)((char *)T.xp + 2 * off) = w;
+    vstore<NT>(w, (dvec2 *)((char *)T.xp + 2 * off));
 }
 
 // r and w (y / z / q) at the element offset off, each in its own vector
-__device__ __forceinline__ dvec2 ry_get(const Tile &T, unsigned off) {
+template <bool NT>
+__device__ __forceinline__ dvec2 ry_get(const Tile<NT> &T, unsigned off) {
     dvec2 v;
-    v.x = *(const double *)((const char *)T.r + off);
-    v.y = *(const double *)((const char *)T.w + off);
+    v.x = vload<NT>((const double *)((const char *)T.r + off));
+    v.y = vload<NT>((const double *)((const char *)T.w + off));
     return v;
 }
 
-__device__ __forceinline__ void ry_put(const Tile &T, unsigned off, double r, double y) {
-    *(double *)((char *)T.r + off) = r;
-    *(double *)((char *)T.w + off) = y;
+template <bool NT>
+__device__ __forceinline__ void ry_put(const Tile<NT> &T, unsigned off, double r, double y) {
+    vstore<NT>(r, (double *)((char *)T.r + off));
+    vstore<NT>(y, (double *)((char *)T.w + off));
 }
 
-__device__ __forceinline__ double y_get(const Tile &T, unsigned off) {
-    return *(const double *)((const char *)T.w + off);
+template <bool NT>
+__device__ __forceinline__ double y_get(const Tile<NT> &T, unsigned off) {
+    return vload<NT>((const double *)((const char *)T.w + off));
 }
 
-__device__ __forceinline__ void y_put(const Tile &T, unsigned off, double y) {
-    *(double *)((char *)T.w + off) = y;
+template <bool NT>
+__device__ __forceinline__ void y_put(const Tile<NT> &T, unsigned off, double y) {
+    vstore<NT>(y, (double *)((char *)T.w + off));
 }
 
 // Programs end with kPadSteps idle steps, more than the deepest prefetch
@@ -305,16 +340,16 @@ struct FwdVec {
     double r, q;
 };
 
-template <int S>
-__device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile &T, int sc) {
+template <int S, bool NT>
+__device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, h.x & kBwdRowMask, sc);  // packed record (see the backward solve)
     const dvec2 rq = ry_get(T, o);  // r and q (q sits where y and z were)
     v.r = rq.x;
     v.q = rq.y;
 }
 
-template <int S, int D>
-__device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+template <int S, int D, bool NT>
+__device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                                    double alpha) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
@@ -382,8 +417,8 @@ __device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring
     return out;
 }
 
-template <int S, int D>
-__device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+template <int S, int D, bool NT>
+__device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                    int rs, int sc, double alpha) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
     using St = Stage<S, K>;
@@ -469,8 +504,8 @@ __device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring
 }
 
 // returns {||r||^2, y' D^-1 y} of this lane's rows
-template <int S, int D>
-__device__ __forceinline__ dvec2 fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+template <int S, int D, bool NT>
+__device__ __forceinline__ dvec2 fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                            int sc, double alpha) {
     if constexpr (Stage<S, kEntTri>::kOn)
         return fwd_sweep_staged<S, D>(g, ring, stage, T, rs, sc, alpha);
@@ -494,8 +529,8 @@ struct BwdVec {
 };
 
 // RZ: the sweep forms r'z (reads r); else only y
-template <int S, bool RZ>
-__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile &T, int sc) {
+template <int S, bool RZ, bool NT>
+__device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, bwd_row(h), sc);
     if constexpr (RZ) {
         const dvec2 ry = ry_get(T, o);
@@ -506,8 +541,8 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile &T,
         v.r = 0.0;
     }
 }
-template <int S, int D, bool RZ>
-__device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+template <int S, int D, bool RZ, bool NT>
+__device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                                    int lo, int hi) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
     static_assert(H % E == 0 && E >= 3, "entry slots must tile the unrolled loop");
@@ -568,8 +603,8 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
     return rz;
 }
 
-template <int S, int D, bool RZ>
-__device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+template <int S, int D, bool RZ, bool NT>
+__device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                    int rs, int sc, int lo, int hi) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
     using St = Stage<S, K>;
@@ -647,8 +682,8 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     return rz;
 }
 
-template <int S, int D, bool RZ>
-__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+template <int S, int D, bool RZ, bool NT>
+__device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                             int sc, int lo, int hi) {
     if constexpr (Stage<S, kEntTri>::kOn)
         return bwd_sweep_staged<S, D, RZ>(g, ring, stage, T, rs, sc, lo, hi);
@@ -663,8 +698,8 @@ struct ProdVec {
     double z, p, x;
 };
 
-template <int S>
-__device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &T, int sc) {
+template <int S, bool NT>
+__device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
     v.z = y_get(T, o);
     const dvec2 xp = xp_get(T, o);
@@ -672,8 +707,8 @@ __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile &
     v.p = xp.y;
 }
 
-template <int S, int D>
-__device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ring, const Tile &T, int rs, int sc,
+template <int S, int D, bool NT>
+__device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                              double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
                                              double bc) {
     constexpr int H = 2 * D, E = kEntAheadProd;
@@ -740,8 +775,8 @@ __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ri
     return pq;
 }
 
-template <int S, int D>
-__device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile &T,
+template <int S, int D, bool NT>
+__device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                     int rs, int sc, double alpha, double beta, bool done, int lo,
                                                     int hi, int ic, int jc, double bc) {
     constexpr int H = 2 * D, K = kEntProd;
@@ -829,8 +864,8 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
     return pq;
 }
 
-template <int S, int D>
-__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int4 *stage, const Tile &T, int rs,
+template <int S, int D, bool NT>
+__device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                              int sc, double alpha, double beta, bool done, int lo, int hi, int ic,
                                              int jc, double bc) {
     if constexpr (Stage<S, kEntProd>::kOn)
@@ -841,8 +876,8 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int
 
 // delta += alpha p over every row (the update the product sweep would have
 // made next, applied once the tile stops)
-template <int S>
-__device__ __forceinline__ void final_update(const Tile &T, int rs, int sc, double alpha) {
+template <int S, bool NT>
+__device__ __forceinline__ void final_update(const Tile<NT> &T, int rs, int sc, double alpha) {
     constexpr int R = kWave / S;
     for (int i = rs; i < T.nr; i += R) {
         const unsigned o = sweep_off<S>(T, i, sc);
@@ -880,8 +915,8 @@ struct Col {
 // the zero start; delta = p = q = 0.  Every lane runs the loops and the
 // column sums (the butterflies need the whole wave); only taking columns
 // touch memory.  Returns the column's squared residual norm.
-template <int S>
-__device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T, int rs, int sc, bool take, int scen,
+template <int S, bool NT>
+__device__ __forceinline__ double column_init(const PcgParams &p, const Tile<NT> &T, int rs, int sc, bool take, int scen,
                                               Col &col) {
     constexpr int R = kWave / S;
     const int nr = p.n_r;
@@ -975,8 +1010,8 @@ __device__ __forceinline__ double column_init(const PcgParams &p, const Tile &T,
 // per-scenario right-hand sides and the zero start) on the main system, 0 on
 // islanded buses and at the slack; its step count, status and re-dispatch
 // factor.  Only retiring columns touch memory.
-template <int S>
-__device__ __forceinline__ void column_retire(const PcgParams &p, const Tile &T, int rs, int sc, bool retire,
+template <int S, bool NT>
+__device__ __forceinline__ void column_retire(const PcgParams &p, const Tile<NT> &T, int rs, int sc, bool retire,
                                               const Col &c) {
     constexpr int R = kWave / S;
     if (!retire) return;
@@ -1001,8 +1036,8 @@ __device__ __forceinline__ void column_retire(const PcgParams &p, const Tile &T,
 // every column is busy or the queue is empty.  A column whose new scenario
 // stops at once (a bad id, a start that already meets the stop test) is
 // retired and refilled in the next round.
-template <int S>
-__device__ __forceinline__ void refill(const PcgParams &p, const Tile &T, int rs, int sc, Col &col, bool &done,
+template <int S, bool NT>
+__device__ __forceinline__ void refill(const PcgParams &p, const Tile<NT> &T, int rs, int sc, Col &col, bool &done,
                                        double &alpha, double &rho, bool &drained) {
     const int lane = threadIdx.x;
     for (;;) {
@@ -1039,12 +1074,12 @@ __device__ __forceinline__ void refill(const PcgParams &p, const Tile &T, int rs
 // factors), beta, product sweep (delta += alpha p_old, p = z + beta p, q = A_c p with
 // the outaged branch shielded, p'q), alpha.  Returns the iterations the wave
 // ran (sweeps of its columns, counting stopped ones).
-template <int S, int D, int DP>
+template <int S, int D, int DP, bool NT>
 __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, double *ring) {
     const int lane = threadIdx.x;
     const int sc = lane % S;
     const int rs = lane / S;
-    Tile T;
+    Tile<NT> T;
     for (int v = 0; v < kVectors; ++v) T.v[v] = p.ws + (size_t)wave * p.ws_slot + (size_t)v * vec_stride(p.n_r, S);
     T.xp = T.v[0];
     T.r = T.v[2];
@@ -1135,11 +1170,11 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
     return sweeps;
 }
 
-// Work-group b (one wavefront) is persistent wave b.
-template <int S, int D, int DP>
+// Work-group b (one wavefront) is persistent wave b; NT as for Tile.
+template <int S, int D, int DP, bool NT>
 __global__ void __launch_bounds__(kWave) pcg_wave_kernel(PcgParams p) {
     extern __shared__ double ring[];
-    const long long n = pcg_wave<S, D, DP>(p, blockIdx.x, ring);
+    const long long n = pcg_wave<S, D, DP, NT>(p, blockIdx.x, ring);
     if (p.sweeps && threadIdx.x == 0) atomicAdd(p.sweeps, (unsigned long long)n);
 }
 
@@ -1147,13 +1182,13 @@ __global__ void __launch_bounds__(kWave) pcg_wave_kernel(PcgParams p) {
 // the caller's order (heaviest first), each until that grid's queue is
 // empty and its own columns have stopped, so waves done with a large grid
 // move on to the smaller ones while the others finish.
-template <int S, int D, int DP>
+template <int S, int D, int DP, bool NT>
 __global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, int n_grids) {
     extern __shared__ double ring[];
     long long n = 0;
     for (int g = 0; g < n_grids; ++g) {
         const PcgParams &p = grids[g];
-        n += pcg_wave<S, D, DP>(p, blockIdx.x, ring);
+        n += pcg_wave<S, D, DP, NT>(p, blockIdx.x, ring);
         __syncthreads();
     }
     if (grids[0].sweeps && threadIdx.x == 0) atomicAdd(grids[0].sweeps, (unsigned long long)n);
@@ -1179,8 +1214,11 @@ __global__ void queue_reset_kernel(const PcgParams *grids, int n_grids, int32_t 
 // ---------------------------------------------------------------------------
 
 template <int S>
-static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, hipStream_t st) {
-    auto kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd>;
+static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, bool stream, hipStream_t st) {
+    auto kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd, false>;
+    if constexpr (S > 1) {  // one column per wave (the base-case solve) has no idle columns to ease
+        if (stream) kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd, true>;
+    }
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1192,8 +1230,12 @@ static hipError_t launch_wave_s(const PcgParams &prm, int n_waves, size_t lds, h
 }
 
 template <int S>
-static hipError_t launch_multi_s(const PcgParams *grids, int n_grids, int n_waves, size_t lds, hipStream_t st) {
-    auto kern = pcg_multi_kernel<S, kPrefetchTri, kPrefetchProd>;
+static hipError_t launch_multi_s(const PcgParams *grids, int n_grids, int n_waves, size_t lds, bool stream,
+                                 hipStream_t st) {
+    auto kern = pcg_multi_kernel<S, kPrefetchTri, kPrefetchProd, false>;
+    if constexpr (S > 1) {
+        if (stream) kern = pcg_multi_kernel<S, kPrefetchTri, kPrefetchProd, true>;
+    }
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1209,12 +1251,18 @@ static int max_waves_s(size_t lds) {
     int per_cu = 0, cu = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    auto kern = pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd>;
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kWave, lds) != hipSuccess) return 0;
-    return per_cu * cu;
+    // the smaller occupancy of the two cache-policy forms (they differ in the hint only)
+    const void *kerns[2] = {(const void *)pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd, false>,
+                            (const void *)pcg_wave_kernel<S, kPrefetchTri, kPrefetchProd, S != 1>};
+    int best = INT_MAX;
+    for (const void *kern : kerns) {
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess) return 0;
+        best = std::min(best, per_cu);
+    }
+    return best * cu;
 }
 
 static size_t ring_lds(int ring_rows, int S) {
@@ -1237,32 +1285,33 @@ int pcg_max_waves(int S, int ring_rows) {
     }
 }
 
-hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, hipStream_t st) {
+hipError_t launch_pcg_multi(const PcgParams *grids, int n_grids, int S, int n_waves, int ring_rows, bool stream,
+                            hipStream_t st) {
     if (n_waves <= 0 || n_grids <= 0) return hipSuccess;
     const size_t lds = ring_lds(ring_rows, S);
     switch (S) {
-        case 1: return launch_multi_s<1>(grids, n_grids, n_waves, lds, st);
-        case 2: return launch_multi_s<2>(grids, n_grids, n_waves, lds, st);
-        case 4: return launch_multi_s<4>(grids, n_grids, n_waves, lds, st);
-        case 8: return launch_multi_s<8>(grids, n_grids, n_waves, lds, st);
-        case 16: return launch_multi_s<16>(grids, n_grids, n_waves, lds, st);
-        case 32: return launch_multi_s<32>(grids, n_grids, n_waves, lds, st);
-        case 64: return launch_multi_s<64>(grids, n_grids, n_waves, lds, st);
+        case 1: return launch_multi_s<1>(grids, n_grids, n_waves, lds, stream, st);
+        case 2: return launch_multi_s<2>(grids, n_grids, n_waves, lds, stream, st);
+        case 4: return launch_multi_s<4>(grids, n_grids, n_waves, lds, stream, st);
+        case 8: return launch_multi_s<8>(grids, n_grids, n_waves, lds, stream, st);
+        case 16: return launch_multi_s<16>(grids, n_grids, n_waves, lds, stream, st);
+        case 32: return launch_multi_s<32>(grids, n_grids, n_waves, lds, stream, st);
+        case 64: return launch_multi_s<64>(grids, n_grids, n_waves, lds, stream, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, hipStream_t st) {
+hipError_t launch_pcg(const PcgParams &prm, int S, int n_waves, int ring_rows, bool stream, hipStream_t st) {
     if (n_waves <= 0) return hipSuccess;
     const size_t lds = ring_lds(ring_rows, S);
     switch (S) {
-        case 1: return launch_wave_s<1>(prm, n_waves, lds, st);
-        case 2: return launch_wave_s<2>(prm, n_waves, lds, st);
-        case 4: return launch_wave_s<4>(prm, n_waves, lds, st);
-        case 8: return launch_wave_s<8>(prm, n_waves, lds, st);
-        case 16: return launch_wave_s<16>(prm, n_waves, lds, st);
-        case 32: return launch_wave_s<32>(prm, n_waves, lds, st);
-        case 64: return launch_wave_s<64>(prm, n_waves, lds, st);
+        case 1: return launch_wave_s<1>(prm, n_waves, lds, stream, st);
+        case 2: return launch_wave_s<2>(prm, n_waves, lds, stream, st);
+        case 4: return launch_wave_s<4>(prm, n_waves, lds, stream, st);
+        case 8: return launch_wave_s<8>(prm, n_waves, lds, stream, st);
+        case 16: return launch_wave_s<16>(prm, n_waves, lds, stream, st);
+        case 32: return launch_wave_s<32>(prm, n_waves, lds, stream, st);
+        case 64: return launch_wave_s<64>(prm, n_waves, lds, stream, st);
         default: return hipErrorInvalidValue;
     }
 }
