@@ -199,9 +199,15 @@ __device__ __forceinline__ void stage_read(Ents<K> &E, const int4 *stage, int rs
 }
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
-// the {delta, p} pairs at xp, r, and w (y, then z, then q).  NT selects the
-// cache policy of the sweeps' vector accesses (below).
-template <bool NT>
+// the {delta, p} pairs at xp, r, and w (y, then z, then q).  NT holds the
+// policy bits of the sweeps' vector accesses: kStreamVec, the non-temporal
+// hint (below); kGlobalVec, accesses through global-memory pointers (the
+// batch kernel reads its vector bases from a parameter array in memory, so
+// the compiler cannot prove them global and would issue flat instructions,
+// which also count against the LDS wait counter; 2 % faster there).
+constexpr int kStreamVec = 1, kGlobalVec = 2;
+
+template <int NT>
 struct Tile {
     double *xp, *r, *w;
     double *v[kVectors];
@@ -211,7 +217,7 @@ struct Tile {
 
 // byte offset of (row, column sc) inside any vector of a tile (idle slots
 // name the scratch row n_r)
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ unsigned row_off(const Tile<NT> &T, int row, int sc) {
     return ((unsigned)row * S + sc) * 8u;
 }
@@ -219,7 +225,7 @@ __device__ __forceinline__ unsigned row_off(const Tile<NT> &T, int row, int sc) 
 // the same inside the sweeps: a column without a scenario reads and writes
 // its scratch row only (one cache line, so the finished columns of a wave
 // cost no memory traffic while the others finish)
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ unsigned sweep_off(const Tile<NT> &T, int row, int sc) {
     return ((unsigned)(T.idle ? T.nr : row) * S + sc) * 8u;
 }
@@ -228,7 +234,7 @@ __device__ __forceinline__ unsigned sweep_off(const Tile<NT> &T, int row, int sc
 // one sweep later, after the wave has streamed through the whole vector and
 // the other waves through theirs; where that is more than the Infinity
 // Cache holds (4.3 GB on the 10,000-bus grid at block 16) no cache keeps
-// it, and with NT the accesses carry the non-temporal (streaming) hint,
+// it, and with kStreamVec the accesses carry the non-temporal hint,
 // which leaves L2 to the matrix and factor entries that every wave reads
 // (there: 0.47 TB less read traffic per launch and 3.7 % faster; the hint
 // on loads or on stores alone made no difference).  The hint also streams
@@ -238,25 +244,37 @@ __device__ __forceinline__ unsigned sweep_off(const Tile<NT> &T, int row, int sc
 // overhead near 1.0), the ordinary policy otherwise (the first solve,
 // ranked by the analytic key, sweeps about 1.3 times the busy columns and
 // took 1.91 s instead of 1.57 s with the hint).
-template <bool NT, class V>
+template <int NT, class V>
 __device__ __forceinline__ V vload(const V *a) {
-    if constexpr (NT) return __builtin_nontemporal_load(a);
-    else return *a;
+    if constexpr ((NT & kGlobalVec) != 0) {
+        const __attribute__((address_space(1))) V *g = (const __attribute__((address_space(1))) V *)a;
+        if constexpr ((NT & kStreamVec) != 0) return __builtin_nontemporal_load(g);
+        else return *g;
+    } else {
+        if constexpr ((NT & kStreamVec) != 0) return __builtin_nontemporal_load(a);
+        else return *a;
+    }
 }
 
-template <bool NT, class V>
+template <int NT, class V>
 __device__ __forceinline__ void vstore(V v, V *a) {
-    if constexpr (NT) __builtin_nontemporal_store(v, a);
-    else *a = v;
+    if constexpr ((NT & kGlobalVec) != 0) {
+        __attribute__((address_space(1))) V *g = (__attribute__((address_space(1))) V *)a;
+        if constexpr ((NT & kStreamVec) != 0) __builtin_nontemporal_store(v, g);
+        else *g = v;
+    } else {
+        if constexpr ((NT & kStreamVec) != 0) __builtin_nontemporal_store(v, a);
+        else *a = v;
+    }
 }
 
 // the pair {delta, p} at the element offset off of the other vectors
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ dvec2 xp_get(const Tile<NT> &T, unsigned off) {
     return vload<NT>((const dvec2 *)((const char *)T.xp + 2 * off));
 }
 
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ void xp_put(const Tile<NT> &T, unsigned off, double x, double pv) {
     dvec2 w;
     w.x = x;
@@ -265,7 +283,7 @@ __device__ __forceinline__ void xp_put(const Tile<NT> &T, unsigned off, double x
 }
 
 // r and w (y / z / q) at the element offset off, each in its own vector
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ dvec2 ry_get(const Tile<NT> &T, unsigned off) {
     dvec2 v;
     v.x = vload<NT>((const double *)((const char *)T.r + off));
@@ -273,18 +291,18 @@ __device__ __forceinline__ dvec2 ry_get(const Tile<NT> &T, unsigned off) {
     return v;
 }
 
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ void ry_put(const Tile<NT> &T, unsigned off, double r, double y) {
     vstore<NT>(r, (double *)((char *)T.r + off));
     vstore<NT>(y, (double *)((char *)T.w + off));
 }
 
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ double y_get(const Tile<NT> &T, unsigned off) {
     return vload<NT>((const double *)((const char *)T.w + off));
 }
 
-template <bool NT>
+template <int NT>
 __device__ __forceinline__ void y_put(const Tile<NT> &T, unsigned off, double y) {
     vstore<NT>(y, (double *)((char *)T.w + off));
 }
@@ -340,7 +358,7 @@ struct FwdVec {
     double r, q;
 };
 
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, h.x & kBwdRowMask, sc);  // packed record (see the backward solve)
     const dvec2 rq = ry_get(T, o);  // r and q (q sits where y and z were)
@@ -348,7 +366,7 @@ __device__ __forceinline__ void fwd_vec(FwdVec &v, const int4 &h, const Tile<NT>
     v.q = rq.y;
 }
 
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                                    double alpha) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
@@ -417,7 +435,7 @@ __device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring
     return out;
 }
 
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                    int rs, int sc, double alpha) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
@@ -504,7 +522,7 @@ __device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring
 }
 
 // returns {||r||^2, y' D^-1 y} of this lane's rows
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ dvec2 fwd_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                            int sc, double alpha) {
     if constexpr (Stage<S, kEntTri>::kOn)
@@ -529,7 +547,7 @@ struct BwdVec {
 };
 
 // RZ: the sweep forms r'z (reads r); else only y
-template <int S, bool RZ, bool NT>
+template <int S, bool RZ, int NT>
 __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, bwd_row(h), sc);
     if constexpr (RZ) {
@@ -541,7 +559,7 @@ __device__ __forceinline__ void bwd_vec(BwdVec &v, const int4 &h, const Tile<NT>
         v.r = 0.0;
     }
 }
-template <int S, int D, bool RZ, bool NT>
+template <int S, int D, bool RZ, int NT>
 __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                                    int lo, int hi) {
     constexpr int H = 2 * D, E = kEntAheadTri, K = kEntTri;
@@ -603,7 +621,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
     return rz;
 }
 
-template <int S, int D, bool RZ, bool NT>
+template <int S, int D, bool RZ, int NT>
 __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                    int rs, int sc, int lo, int hi) {
     constexpr int H = 2 * D, EQ = kStageAheadTri, K = kEntTri;
@@ -682,7 +700,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     return rz;
 }
 
-template <int S, int D, bool RZ, bool NT>
+template <int S, int D, bool RZ, int NT>
 __device__ __forceinline__ double bwd_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                             int sc, int lo, int hi) {
     if constexpr (Stage<S, kEntTri>::kOn)
@@ -698,7 +716,7 @@ struct ProdVec {
     double z, p, x;
 };
 
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile<NT> &T, int sc) {
     const unsigned o = sweep_off<S>(T, h.w, sc);  // look-ahead row (or the scratch row)
     v.z = y_get(T, o);
@@ -707,7 +725,7 @@ __device__ __forceinline__ void prod_vec(ProdVec &v, const int4 &h, const Tile<N
     v.p = xp.y;
 }
 
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ring, const Tile<NT> &T, int rs, int sc,
                                              double alpha, double beta, bool done, int lo, int hi, int ic, int jc,
                                              double bc) {
@@ -775,7 +793,7 @@ __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ri
     return pq;
 }
 
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ring, int4 *stage, const Tile<NT> &T,
                                                     int rs, int sc, double alpha, double beta, bool done, int lo,
                                                     int hi, int ic, int jc, double bc) {
@@ -864,7 +882,7 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
     return pq;
 }
 
-template <int S, int D, bool NT>
+template <int S, int D, int NT>
 __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int4 *stage, const Tile<NT> &T, int rs,
                                              int sc, double alpha, double beta, bool done, int lo, int hi, int ic,
                                              int jc, double bc) {
@@ -876,7 +894,7 @@ __device__ __forceinline__ double prod_sweep(const Program &g, double *ring, int
 
 // delta += alpha p over every row (the update the product sweep would have
 // made next, applied once the tile stops)
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ void final_update(const Tile<NT> &T, int rs, int sc, double alpha) {
     constexpr int R = kWave / S;
     for (int i = rs; i < T.nr; i += R) {
@@ -915,7 +933,7 @@ struct Col {
 // the zero start; delta = p = q = 0.  Every lane runs the loops and the
 // column sums (the butterflies need the whole wave); only taking columns
 // touch memory.  Returns the column's squared residual norm.
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ double column_init(const PcgParams &p, const Tile<NT> &T, int rs, int sc, bool take, int scen,
                                               Col &col) {
     constexpr int R = kWave / S;
@@ -1010,7 +1028,7 @@ __device__ __forceinline__ double column_init(const PcgParams &p, const Tile<NT>
 // per-scenario right-hand sides and the zero start) on the main system, 0 on
 // islanded buses and at the slack; its step count, status and re-dispatch
 // factor.  Only retiring columns touch memory.
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ void column_retire(const PcgParams &p, const Tile<NT> &T, int rs, int sc, bool retire,
                                               const Col &c) {
     constexpr int R = kWave / S;
@@ -1036,7 +1054,7 @@ __device__ __forceinline__ void column_retire(const PcgParams &p, const Tile<NT>
 // every column is busy or the queue is empty.  A column whose new scenario
 // stops at once (a bad id, a start that already meets the stop test) is
 // retired and refilled in the next round.
-template <int S, bool NT>
+template <int S, int NT>
 __device__ __forceinline__ void refill(const PcgParams &p, const Tile<NT> &T, int rs, int sc, Col &col, bool &done,
                                        double &alpha, double &rho, bool &drained) {
     const int lane = threadIdx.x;
@@ -1074,7 +1092,7 @@ __device__ __forceinline__ void refill(const PcgParams &p, const Tile<NT> &T, in
 // factors), beta, product sweep (delta += alpha p_old, p = z + beta p, q = A_c p with
 // the outaged branch shielded, p'q), alpha.  Returns the iterations the wave
 // ran (sweeps of its columns, counting stopped ones).
-template <int S, int D, int DP, bool NT>
+template <int S, int D, int DP, int NT>
 __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, double *ring) {
     const int lane = threadIdx.x;
     const int sc = lane % S;
@@ -1170,25 +1188,27 @@ __device__ __forceinline__ long long pcg_wave(const PcgParams &p, int wave, doub
     return sweeps;
 }
 
-// Work-group b (one wavefront) is persistent wave b; NT as for Tile.
+// Work-group b (one wavefront) is persistent wave b; NT: the non-temporal
+// vector accesses (kStreamVec).
 template <int S, int D, int DP, bool NT>
 __global__ void __launch_bounds__(kWave) pcg_wave_kernel(PcgParams p) {
     extern __shared__ double ring[];
-    const long long n = pcg_wave<S, D, DP, NT>(p, blockIdx.x, ring);
+    const long long n = pcg_wave<S, D, DP, NT ? kStreamVec : 0>(p, blockIdx.x, ring);
     if (p.sweeps && threadIdx.x == 0) atomicAdd(p.sweeps, (unsigned long long)n);
 }
 
 // Several grids (the uneven batch): every wave works through the grids in
 // the caller's order (heaviest first), each until that grid's queue is
 // empty and its own columns have stopped, so waves done with a large grid
-// move on to the smaller ones while the others finish.
+// move on to the smaller ones while the others finish.  Its vector accesses
+// go through global-memory pointers (kGlobalVec).
 template <int S, int D, int DP, bool NT>
 __global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, int n_grids) {
     extern __shared__ double ring[];
     long long n = 0;
     for (int g = 0; g < n_grids; ++g) {
         const PcgParams &p = grids[g];
-        n += pcg_wave<S, D, DP, NT>(p, blockIdx.x, ring);
+        n += pcg_wave<S, D, DP, (NT ? kStreamVec : 0) | kGlobalVec>(p, blockIdx.x, ring);
         __syncthreads();
     }
     if (grids[0].sweeps && threadIdx.x == 0) atomicAdd(grids[0].sweeps, (unsigned long long)n);
