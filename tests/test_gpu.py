@@ -369,7 +369,8 @@ def test_grid10k_all_outages(gp, grids):
     """Every outage of the 10,000-bus grid in the benchmark's launch: the
     library's own row order, assembly and ILU(0), block 16, a 64-row
     look-ahead window, stop 1e-12, solved twice (the second solve ranks its
-    queue by the first one's iterations, as the timed solves do).  Angles,
+    queue by the first one's iterations, as the timed solves do, and so runs
+    the kernel's streaming form, the first its ordinary form).  Angles,
     flows, island flags, statuses and true residuals of all 13,500 outages
     of the second solve against the oracle's direct solve, and the first
     solve bit-identical to it.  The two assemblies are bit identical (every
