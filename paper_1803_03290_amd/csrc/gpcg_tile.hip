@@ -95,6 +95,28 @@ __device__ __forceinline__ void ring_put(double *ring, int byte_off, double v) {
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef int ivec4 __attribute__((ext_vector_type(4)));
 
+// Access-policy bits of the sweeps (see Tile).
+constexpr int kStreamVec = 1, kGlobalVec = 2;
+
+// A load of program data (records, entry chunks) under the same policy:
+// with kGlobalVec through a global-memory pointer, as a native vector type
+// (the 16-byte records are class objects, which do not load through one).
+template <int NT, class V>
+__device__ __forceinline__ V pload(const V *a) {
+    if constexpr ((NT & kGlobalVec) != 0) {
+        if constexpr (sizeof(V) == 16 && alignof(V) >= 16) {
+            const ivec4 w = *(const __attribute__((address_space(1))) ivec4 *)a;
+            V v;
+            __builtin_memcpy(&v, &w, 16);
+            return v;
+        } else {
+            return *(const __attribute__((address_space(1))) V *)a;
+        }
+    } else {
+        return *a;
+    }
+}
+
 template <int K>
 struct Ents {
     static_assert(K % 4 == 0, "entry records come in 16-byte chunks");
@@ -116,13 +138,13 @@ __device__ __forceinline__ const int4 *ent_slot(const Program &g, int s, int rs)
     return g.ent + (size_t)s * (3 * K / 4) * R + rs;
 }
 
-template <int S, int K>
+template <int S, int K, int NT>
 __device__ __forceinline__ void load_ents(Ents<K> &E, const int4 *p) {
     constexpr int R = kWave / S;
 #pragma unroll
-    for (int c = 0; c < K / 2; ++c) E.v[c] = *(const dvec2 *)(p + c * R);
+    for (int c = 0; c < K / 2; ++c) E.v[c] = pload<NT>((const dvec2 *)(p + c * R));
 #pragma unroll
-    for (int c = 0; c < K / 4; ++c) E.o[c] = p[(K / 2 + c) * R];
+    for (int c = 0; c < K / 4; ++c) E.o[c] = pload<NT>(p + (K / 2 + c) * R);
 }
 
 // A step's ring values and entry values, gathered before the step's refill
@@ -176,10 +198,10 @@ struct StageLane {
     }
 };
 
-template <int S, int K>
+template <int S, int K, int NT>
 __device__ __forceinline__ void raw_load(ivec4 *q, const int4 *step_base, const StageLane<S, K> &L) {
 #pragma unroll
-    for (int i = 0; i < Stage<S, K>::NL; ++i) q[i] = *(const ivec4 *)(step_base + L.j[i]);
+    for (int i = 0; i < Stage<S, K>::NL; ++i) q[i] = pload<NT>((const ivec4 *)(step_base + L.j[i]));
 }
 
 template <int S, int K>
@@ -200,13 +222,12 @@ __device__ __forceinline__ void stage_read(Ents<K> &E, const int4 *stage, int rs
 
 // A tile's vectors, each (n_r + 1) rows x S columns (row n_r is scratch):
 // the {delta, p} pairs at xp, r, and w (y, then z, then q).  NT holds the
-// policy bits of the sweeps' vector accesses: kStreamVec, the non-temporal
-// hint (below); kGlobalVec, accesses through global-memory pointers (the
-// batch kernel reads its vector bases from a parameter array in memory, so
-// the compiler cannot prove them global and would issue flat instructions,
-// which also count against the LDS wait counter; 2 % faster there).
-constexpr int kStreamVec = 1, kGlobalVec = 2;
-
+// policy bits of the sweeps' accesses: kStreamVec, the non-temporal hint
+// on the vectors (below); kGlobalVec, vector and program accesses through
+// global-memory pointers (the batch kernel reads its bases from a parameter
+// array in memory, so the compiler cannot prove them global and would issue
+// flat instructions, which also count against the LDS wait counter; the
+// batch ran 2 % faster with the vectors cast, 7 % with the programs too).
 template <int NT>
 struct Tile {
     double *xp, *r, *w;
@@ -386,7 +407,7 @@ __device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring
 #pragma unroll
     for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
+    for (int d = 0; d < E; ++d) load_ents<S, K, NT>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -423,9 +444,9 @@ __device__ __forceinline__ dvec2 fwd_sweep_direct(const Program &g, double *ring
                 r = v.r - alpha * v.q;
                 rc = r - carry;
             }
-            load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
+            load_ents<S, K, NT>(eq[d % E], eb + (d + E) * C * R);
             fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = hb[(d + H) * R];
+            hq[d] = pload<NT>(hb + (d + H) * R);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -466,12 +487,12 @@ __device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring
     for (int d = 0; d < D; ++d) fwd_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NB, L);
+        raw_load<S, K, NT>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K, NT>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -510,7 +531,7 @@ __device__ __forceinline__ dvec2 fwd_sweep_staged(const Program &g, double *ring
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
             hq[(d + D + 2) % H] = stage[NC + rs];  // the record of step (d + D + 2)
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
+            raw_load<S, K, NT>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
             fwd_vec<S>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -579,7 +600,7 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
 #pragma unroll
     for (int d = 0; d < D; ++d) bwd_vec<S, RZ>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, K>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
+    for (int d = 0; d < E; ++d) load_ents<S, K, NT>(eq[d], ent_slot<S, K>(g, z0, rs) + d * C * R);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -612,9 +633,9 @@ __device__ __forceinline__ double bwd_sweep_direct(const Program &g, double *rin
                 dv = bwd_dinv(hq[(d + 1) % H]);
                 r = v.r;
             }
-            load_ents<S, K>(eq[d % E], eb + (d + E) * C * R);
+            load_ents<S, K, NT>(eq[d % E], eb + (d + E) * C * R);
             bwd_vec<S, RZ>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
-            hq[d] = hb[(d + H) * R];
+            hq[d] = pload<NT>(hb + (d + H) * R);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -652,12 +673,12 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
     for (int d = 0; d < D; ++d) bwd_vec<S, RZ>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NB, L);
+        raw_load<S, K, NT>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K, NT>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     int ga[K];
     double G[K];
     ring_addr(ga, eq[0], lane_off);
@@ -692,7 +713,7 @@ __device__ __forceinline__ double bwd_sweep_staged(const Program &g, double *rin
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
             hq[(d + D + 2) % H] = stage[NC + rs];  // the record of step (d + D + 2)
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
+            raw_load<S, K, NT>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
             bwd_vec<S, RZ>(vq[(d + 1) % D], hq[(d + 1 + D) % H], T, sc);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -750,7 +771,7 @@ __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ri
 #pragma unroll
     for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
-    for (int d = 0; d < E; ++d) load_ents<S, kEntProd>(eq[d], ent_slot<S, kEntProd>(g, z0, rs) + d * C * R);
+    for (int d = 0; d < E; ++d) load_ents<S, kEntProd, NT>(eq[d], ent_slot<S, kEntProd>(g, z0, rs) + d * C * R);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
         const int4 *hb = head_slot<S>(g, sb, rs);
@@ -769,8 +790,8 @@ __device__ __forceinline__ double prod_sweep_direct(const Program &g, double *ri
             const double pf = ring_at(ring, ic_off), pt = ring_at(ring, jc_off);
             const double pown = ring_at(ring, h.y + lane_off);
             prod_vec<S>(vq[d % D], hq[(d + D) % H], T, sc);
-            load_ents<S, kEntProd>(eq[d % E], eb + (d + E) * C * R);
-            hq[d] = hb[(d + H) * R];
+            load_ents<S, kEntProd, NT>(eq[d % E], eb + (d + E) * C * R);
+            hq[d] = pload<NT>(hb + (d + H) * R);
             {
                 xp_put(T, lo_, v.x + alpha * v.p, pn);
                 const double dot = gdot(G);
@@ -830,12 +851,12 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
     for (int d = 0; d < D; ++d) prod_vec<S>(vq[d], hq[d], T, sc);
 #pragma unroll
     for (int d = 0; d < LA; ++d) {
-        raw_load<S, K>(q[0], qb0 + d * NB, L);
+        raw_load<S, K, NT>(q[0], qb0 + d * NB, L);
         raw_put<S, K>(stage, q[0], lane);
         stage_read<S, K>(eq[d], stage, rs);
     }
 #pragma unroll
-    for (int d = 0; d < EQ; ++d) raw_load<S, K>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
+    for (int d = 0; d < EQ; ++d) raw_load<S, K, NT>(q[(d + LA) % EQ], qb0 + (d + LA) * NB, L);
     for (int s0 = 0; s0 < g.steps; s0 += H) {
         const int sb = opaque(s0);  // step base: every address below is a constant offset from it
         const int4 *qb = g.ent + (size_t)sb * NB;
@@ -858,7 +879,7 @@ __device__ __forceinline__ double prod_sweep_staged(const Program &g, double *ri
             raw_put<S, K>(stage, q[(d + LA) % EQ], lane);
             stage_read<S, K>(eq[(d + LA) % NE], stage, rs);
             hq[(d + D + 1) % H] = stage[NC + rs];  // the record of step (d + D + 1)
-            raw_load<S, K>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
+            raw_load<S, K, NT>(q[(d + LA) % EQ], qb + (d + LA + EQ) * NB, L);
 
             {
                 xp_put(T, lo_, v.x + alpha * v.p, pn);
@@ -1200,8 +1221,8 @@ __global__ void __launch_bounds__(kWave) pcg_wave_kernel(PcgParams p) {
 // Several grids (the uneven batch): every wave works through the grids in
 // the caller's order (heaviest first), each until that grid's queue is
 // empty and its own columns have stopped, so waves done with a large grid
-// move on to the smaller ones while the others finish.  Its vector accesses
-// go through global-memory pointers (kGlobalVec).
+// move on to the smaller ones while the others finish.  Its vector and
+// program accesses go through global-memory pointers (kGlobalVec).
 template <int S, int D, int DP, bool NT>
 __global__ void __launch_bounds__(kWave) pcg_multi_kernel(const PcgParams *grids, int n_grids) {
     extern __shared__ double ring[];
