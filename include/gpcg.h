@@ -261,7 +261,10 @@ int gpcg_get_perm(gpcg_t h, int32_t *perm);
  * has solved before is ranked by the iterations it took then, others first
  * (the context keeps one iteration record per outage id and start mode).
  * The order changes no result: every scenario's arithmetic is the same in
- * any column.  Workspace (4 (n_r + 1) S doubles per wavefront) is owned by
+ * any column.  Once the context has an iteration record and the workspace
+ * exceeds 256 MB (more than the Infinity Cache holds), the sweeps stream
+ * their vectors past the caches (a cache hint; the results are the same).
+ * Workspace (4 (n_r + 1) S doubles per wavefront) is owned by
  * the context and grows on demand.  Errors: GPCG_E_ARG for NULL required pointers, n_out < 0,
  * max_iter < 1, or flows requested from a B'' context.  Outage ids are read
  * on the device only: an id outside [-1, m) gives that scenario status
