@@ -1074,7 +1074,7 @@ __device__ __forceinline__ void column_retire(const PcgParams &p, const Tile<NT>
 // Retire every stopped column and refill the free ones from the queue, until
 // every column is busy or the queue is empty.  A column whose new scenario
 // stops at once (a bad id, a start that already meets the stop test) is
-// retired and refilled in the next round.
+// retired and refilled in the next pass of the loop.
 template <int S, int NT>
 __device__ __forceinline__ void refill(const PcgParams &p, const Tile<NT> &T, int rs, int sc, Col &col, bool &done,
                                        double &alpha, double &rho, bool &drained) {
